@@ -1,0 +1,155 @@
+/*
+ * vanse.h -- C ABI of the MI355X (gfx950) implementation of the consistent
+ * lattice Boltzmann scheme for the volume averaged Navier-Stokes equations
+ * (VANSE) of Bukreev, Simonis, Kummerlaender, Jessberger and Krause,
+ * arXiv:2208.09267, Section "Lattice Boltzmann scheme for VANSE".
+ *
+ * One solver handle owns one periodic lattice and advances it with the
+ * fused per-cell step
+ *
+ *   I   = phi + varpi * lap(phi)                  cell integral of phi
+ *                                                  (eqs. quad / latDiffRuleIIre,
+ *                                                  Table 3 weights)
+ *   rho = sum_i f_i / I                            eq. density
+ *   p   = rho c_s^2,  F = p grad(phi) + F_ext      eq. pressForce (central
+ *                                                  differences of phi)
+ *   u   = (sum_i xi_i f_i + F/2) / sum_i f_i       eq. velocity
+ *   f_i(x + xi_i, t + 1) = f_i - (f_i - f_i^eq)/tau + Omega^F_i
+ *                                                  eq. lbe, eq. feq (with
+ *                                                  rho I = sum f), Guo forcing
+ *
+ * in lattice units (dx = dt = 1, c_s^2 = 1/3).  The volume fraction is
+ * phi(x, t_n) = eps_mean + m(n) eps_pert(x) with m(n) = cos(2 pi n / period)
+ * (m = 1 when period <= 0); every term of step n uses phi at t_n.
+ *
+ * Conventions for every function below
+ *   - Return value: VANSE_OK (0) or a negative VANSE_E* status.  No C++
+ *     exception crosses the ABI.  vanse_last_error(h) describes the last
+ *     failure on h.
+ *   - Array arguments are DEVICE pointers owned by the caller (e.g. the data
+ *     of contiguous torch tensors on the current GPU), FP64, x fastest:
+ *     cell = (z*ny + y)*nx + x.  Vector fields are SoA: u[a*ncells + cell].
+ *     The library never keeps a caller pointer past the call.
+ *   - Work is enqueued on the handle's stream (vanse_set_stream; default the
+ *     null stream) and is asynchronous unless stated otherwise.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef VANSE_H
+#define VANSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vanse_solver *vanse_t;
+
+/* Lattices: D2Q9 (Table 1) and D3Q19 (the rest, face and edge groups of
+ * Table 2 with weights 1/3, 1/18, 1/36). */
+enum { VANSE_D2Q9 = 0, VANSE_D3Q19 = 1 };
+
+/* Population storage.  FP64: f_i in binary64, FP64 arithmetic.
+ * FP32_SHIFTED: g_i = f_i - w_i in binary32, FP32 arithmetic in deviation
+ * form.  FP16_SHIFTED: h_i = (f_i - w_i)/w_i in binary16, FP32 arithmetic.
+ * In the reduced modes eps_pert is held in binary32. */
+enum { VANSE_FP64 = 0, VANSE_FP32_SHIFTED = 1, VANSE_FP16_SHIFTED = 2 };
+
+enum {
+    VANSE_OK = 0,
+    VANSE_EINVAL = -1,    /* bad argument (message in vanse_last_error)    */
+    VANSE_ENOMEM = -2,    /* device allocation failed                      */
+    VANSE_EDEVICE = -3,   /* HIP runtime error                             */
+    VANSE_ESTATE = -4,    /* call out of order (e.g. step before init)     */
+    VANSE_EUNSTABLE = -5  /* diagnostics saw a non-finite value (sticky)   */
+};
+
+/* Create a solver on the current HIP device.
+ *   lattice  VANSE_D2Q9 or VANSE_D3Q19
+ *   dims     {nx, ny, nz}, each >= 1; nz must be 1 for D2Q9;
+ *            nx*ny*nz < 2^31
+ *   tau      BGK relaxation time, finite and > 1/2 (eq. lbe; the recovered
+ *            viscosity is nu = (tau - 1/2) c_s^2)
+ *   dtype    VANSE_FP64, VANSE_FP32_SHIFTED or VANSE_FP16_SHIFTED
+ *   out      receives the handle
+ * Allocates the single in-place population array (AA pattern), the phi
+ * perturbation copy and the reduction scratch with hipMalloc; all are freed
+ * by vanse_destroy.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int vanse_create(int lattice, const int64_t dims[3], double tau, int dtype, vanse_t *out);
+
+/* Free every device allocation of h.  h may be NULL.  Synchronises h's
+ * stream first. */
+int vanse_destroy(vanse_t h);
+
+/* Launch all later work of h on stream (a hipStream_t; NULL = null stream). */
+int vanse_set_stream(vanse_t h, void *stream);
+
+/* Volume fraction phi(x, t_n) = eps_mean + m(n) eps_pert(x), m(n) =
+ * cos(2 pi n / period), period <= 0 meaning m == 1 (static field).
+ *   eps_pert   device FP64 [ncells], or NULL for a uniform field; copied
+ *              (converted to FP32 in the reduced modes), so the caller may
+ *              free it on return
+ *   quad_axes  bitmask of the axes the cell-integral quadrature runs over
+ *              (1 = x, 2 = y, 4 = z; the D1Q3 / D2Q5 / D3Q7 choice of the
+ *              paper, diagonals excluded); 0 selects all d axes
+ * Validates on the device that phi stays in (0, 1] for every reachable m and
+ * that eps_pert is finite; synchronises.  Errors: EINVAL, EDEVICE. */
+int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, double period,
+                       int quad_axes);
+
+/* Constant external force density F_ext (host array of 3 doubles, lattice
+ * units), added to the pressure-correction force in sum_k F_k.  Components
+ * beyond the lattice dimension must be 0.  Errors: EINVAL. */
+int vanse_set_force(vanse_t h, const double F[3]);
+
+/* Initial populations (eq. equilibrium): f_i = f_i^eq of M0 = rho0 phi(x, 0)
+ * and u0, with no non-equilibrium part.  rho0: device FP64 [ncells] or NULL
+ * (1); u0: device FP64 SoA [d][ncells] or NULL (0).  Resets the time to 0.
+ * Requires vanse_set_porosity.  Errors: ESTATE, EDEVICE. */
+int vanse_init(vanse_t h, const double *rho0, const double *u0);
+
+/* Advance n >= 0 time steps (asynchronous).  Errors: ESTATE, EINVAL,
+ * EDEVICE. */
+int vanse_step(vanse_t h, int64_t n);
+
+/* Macroscopic fields at the current time t_n (eqs. density, velocity,
+ * pressForce): rho [ncells], p [ncells], u SoA [d][ncells]; any may be NULL.
+ * Computed in FP64 from the stored populations.  Asynchronous. */
+int vanse_moments(vanse_t h, double *rho, double *p, double *u);
+
+/* Global FP64 sums at t_n, in a fixed (deterministic) order, written to the
+ * HOST array out[7]: out[0] = sum_x sum_i f_i (the phi-weighted mass
+ * sum rho I), out[1..3] = sum_x sum_i xi_i f_i, out[4..6] = sum_x F.
+ * Synchronises.  A non-finite sum makes h sticky-unstable: this and every
+ * later vanse_step return EUNSTABLE. */
+int vanse_diagnostics(vanse_t h, double out[7]);
+
+/* Populations f_i(x, t_n) in FP64, natural order, SoA [Q][ncells] in this
+ * library's direction order (vanse_lattice_info).  Asynchronous. */
+int vanse_populations(vanse_t h, double *f);
+
+/* Current time level n (number of steps since vanse_init). */
+int vanse_time(vanse_t h, int64_t *t);
+
+/* Bytes of device memory held by h. */
+int vanse_device_bytes(vanse_t h, int64_t *bytes);
+
+/* Human-readable description of the last error on h (or of the last failed
+ * vanse_create when h is NULL).  Never NULL; valid until the next call on
+ * h. */
+const char *vanse_last_error(vanse_t h);
+
+/* This library's lattice tables: d, Q, xi (host int [Q][3]) and w (host
+ * double [Q]), in the direction order used by vanse_populations. */
+int vanse_lattice_info(int lattice, int *d, int *q, int *xi, double *w);
+
+/* Streaming copy of `bytes` bytes (multiple of 16) from src to dst on
+ * stream: the achievable-bandwidth probe used to calibrate measurements.
+ * Errors: EINVAL, EDEVICE. */
+int vanse_copy_probe(void *dst, const void *src, int64_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VANSE_H */

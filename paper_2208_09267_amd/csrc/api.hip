@@ -1,0 +1,351 @@
+// api.hip -- host side of the C ABI declared in include/vanse.h: argument
+// validation, ownership of device memory, time stepping and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/vanse.h"
+#include "internal.h"
+#include "lattice.h"
+
+struct vanse_solver {
+    vanse::Solver s;
+};
+
+namespace vanse {
+
+// Modulation of the volume fraction, phi(x, t_n) = eps_mean + m(n) pert(x).
+double modulation(int64_t n, double period)
+{
+    if (!(period > 0.0)) return 1.0;
+    return std::cos(2.0 * M_PI * (double)n / period);
+}
+
+StepArgs step_args(const Solver &s, int64_t n)
+{
+    StepArgs a;
+    a.geo = s.geo;
+    a.f = s.f;
+    a.pert = s.pert;
+    a.eps_mean = s.eps_mean;
+    a.m = modulation(n, s.period);
+    a.omega = 1.0 / s.tau;
+    a.fcoef = 1.0 - 0.5 * a.omega;
+    for (int d = 0; d < 3; ++d) a.F[d] = s.F[d];
+    int n_axes = 0;
+    for (int b = 0; b < 3; ++b) n_axes += (s.qmask >> b) & 1;
+    a.wq = quad_weight(n_axes);
+    a.n2 = 2.0 * n_axes;
+    a.qmask = s.qmask;
+    return a;
+}
+
+}  // namespace vanse
+
+using vanse::Solver;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(Solver *s, int code, const std::string &msg)
+{
+    if (s)
+        s->err = msg;
+    else
+        g_create_error = msg;
+    return code;
+}
+
+int hip_fail(Solver *s, hipError_t e, const char *where)
+{
+    return fail(s, VANSE_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t elem_bytes(int mode)
+{
+    return mode == vanse::MODE_F64 ? 8 : (mode == vanse::MODE_F32S ? 4 : 2);
+}
+
+}  // namespace
+
+extern "C" {
+
+int vanse_create(int lattice, const int64_t dims[3], double tau, int dtype, vanse_t *out)
+{
+    if (!out) return fail(nullptr, VANSE_EINVAL, "vanse_create: out is NULL");
+    *out = nullptr;
+    if (lattice != VANSE_D2Q9 && lattice != VANSE_D3Q19)
+        return fail(nullptr, VANSE_EINVAL, "vanse_create: unknown lattice");
+    if (dtype != VANSE_FP64 && dtype != VANSE_FP32_SHIFTED && dtype != VANSE_FP16_SHIFTED)
+        return fail(nullptr, VANSE_EINVAL, "vanse_create: unknown dtype");
+    if (!dims) return fail(nullptr, VANSE_EINVAL, "vanse_create: dims is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > (1 << 30))
+            return fail(nullptr, VANSE_EINVAL, "vanse_create: every dim must be >= 1");
+    if (lattice == VANSE_D2Q9 && dims[2] != 1)
+        return fail(nullptr, VANSE_EINVAL, "vanse_create: nz must be 1 for D2Q9");
+    const int64_t ncells = dims[0] * dims[1] * dims[2];
+    if (ncells >= (int64_t(1) << 31) || dims[0] * dims[1] >= (int64_t(1) << 31))
+        return fail(nullptr, VANSE_EINVAL, "vanse_create: nx*ny*nz must be < 2^31");
+    if (!std::isfinite(tau) || !(tau > 0.5))
+        return fail(nullptr, VANSE_EINVAL, "vanse_create: tau must be finite and > 1/2");
+
+    auto *h = new (std::nothrow) vanse_solver();
+    if (!h) return fail(nullptr, VANSE_ENOMEM, "vanse_create: host allocation failed");
+    Solver &s = h->s;
+    s.lattice = lattice;
+    s.mode = dtype;
+    s.d = lattice == VANSE_D2Q9 ? 2 : 3;
+    s.q = lattice == VANSE_D2Q9 ? 9 : 19;
+    s.geo.nx = (int)dims[0];
+    s.geo.ny = (int)dims[1];
+    s.geo.nz = (int)dims[2];
+    s.geo.nxy = (int)(dims[0] * dims[1]);
+    s.geo.ncells = (int)ncells;
+    s.geo.stride = (ncells + 127) / 128 * 128;
+    s.tau = tau;
+    s.qmask = s.d == 2 ? 3 : 7;
+
+    s.f_bytes = (size_t)s.q * (size_t)s.geo.stride * elem_bytes(dtype);
+    s.pert_bytes = (size_t)s.geo.stride * (dtype == VANSE_FP64 ? 8 : 4);
+    s.scratch_bytes = sizeof(double) * (7 * vanse::kReduceBlocks + 64);
+    hipError_t e;
+    if ((e = hipMalloc(&s.f, s.f_bytes)) != hipSuccess ||
+        (e = hipMalloc(&s.pert, s.pert_bytes)) != hipSuccess ||
+        (e = hipMalloc((void **)&s.scratch, s.scratch_bytes)) != hipSuccess) {
+        (void)hipFree(s.f);
+        (void)hipFree(s.pert);
+        (void)hipFree(s.scratch);
+        delete h;
+        (void)hipGetLastError();
+        return fail(nullptr, VANSE_ENOMEM,
+                    std::string("vanse_create: hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    *out = h;
+    return VANSE_OK;
+}
+
+int vanse_destroy(vanse_t h)
+{
+    if (!h) return VANSE_OK;
+    Solver &s = h->s;
+    (void)hipStreamSynchronize(s.stream);
+    (void)hipFree(s.f);
+    (void)hipFree(s.pert);
+    (void)hipFree(s.scratch);
+    delete h;
+    return VANSE_OK;
+}
+
+int vanse_set_stream(vanse_t h, void *stream)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_set_stream: NULL handle");
+    h->s.stream = static_cast<hipStream_t>(stream);
+    return VANSE_OK;
+}
+
+int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, double period,
+                       int quad_axes)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_set_porosity: NULL handle");
+    Solver &s = h->s;
+    if (!std::isfinite(eps_mean) || !std::isfinite(period))
+        return fail(&s, VANSE_EINVAL, "vanse_set_porosity: eps_mean and period must be finite");
+    if (quad_axes < 0 || quad_axes > 7 || (s.d == 2 && (quad_axes & 4)))
+        return fail(&s, VANSE_EINVAL, "vanse_set_porosity: bad quad_axes mask");
+    hipError_t e;
+    if (eps_pert) {
+        if (s.mode == vanse::MODE_F64)
+            e = hipMemcpyAsync(s.pert, eps_pert, sizeof(double) * s.geo.ncells,
+                               hipMemcpyDeviceToDevice, s.stream);
+        else
+            e = vanse::launch_convert_pert(s, eps_pert);
+    } else {
+        e = hipMemsetAsync(s.pert, 0, s.pert_bytes, s.stream);
+    }
+    if (e != hipSuccess) return hip_fail(&s, e, "vanse_set_porosity");
+    // range check of the stored perturbation on the device
+    double *partials = s.scratch;
+    if ((e = vanse::launch_pert_range(s, partials)) != hipSuccess)
+        return hip_fail(&s, e, "vanse_set_porosity");
+    static thread_local double host[3 * vanse::kReduceBlocks];
+    if ((e = hipMemcpyAsync(host, partials, sizeof(double) * 3 * vanse::kReduceBlocks,
+                            hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(s.stream)) != hipSuccess)
+        return hip_fail(&s, e, "vanse_set_porosity");
+    double lo = 1e300, hi = -1e300, bad = 0.0;
+    for (int b = 0; b < vanse::kReduceBlocks; ++b) {
+        lo = std::fmin(lo, host[3 * b]);
+        hi = std::fmax(hi, host[3 * b + 1]);
+        bad += host[3 * b + 2];
+    }
+    if (bad > 0.0) return fail(&s, VANSE_EINVAL, "vanse_set_porosity: eps_pert is not finite");
+    if (lo > hi) lo = hi = 0.0;
+    // reachable range of phi = eps_mean + m pert: m in [-1, 1] if periodic, else m = 1
+    double pmin, pmax;
+    if (period > 0.0) {
+        const double amp = std::fmax(std::fabs(lo), std::fabs(hi));
+        pmin = eps_mean - amp;
+        pmax = eps_mean + amp;
+    } else {
+        pmin = eps_mean + lo;
+        pmax = eps_mean + hi;
+    }
+    if (!(pmin > 0.0) || !(pmax <= 1.0)) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "vanse_set_porosity: volume fraction reaches [%g, %g], outside (0, 1]",
+                      pmin, pmax);
+        return fail(&s, VANSE_EINVAL, buf);
+    }
+    s.eps_mean = eps_mean;
+    s.period = period;
+    s.qmask = quad_axes == 0 ? (s.d == 2 ? 3 : 7) : quad_axes;
+    s.porosity_set = true;
+    return VANSE_OK;
+}
+
+int vanse_set_force(vanse_t h, const double F[3])
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_set_force: NULL handle");
+    Solver &s = h->s;
+    if (!F) return fail(&s, VANSE_EINVAL, "vanse_set_force: F is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(F[a])) return fail(&s, VANSE_EINVAL, "vanse_set_force: F not finite");
+        if (a >= s.d && F[a] != 0.0)
+            return fail(&s, VANSE_EINVAL, "vanse_set_force: z force on a 2-D lattice");
+    }
+    for (int a = 0; a < 3; ++a) s.F[a] = F[a];
+    return VANSE_OK;
+}
+
+int vanse_init(vanse_t h, const double *rho0, const double *u0)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_init: NULL handle");
+    Solver &s = h->s;
+    if (!s.porosity_set) return fail(&s, VANSE_ESTATE, "vanse_init: call vanse_set_porosity first");
+    hipError_t e = vanse::launch_init(s, rho0, u0);
+    if (e != hipSuccess) return hip_fail(&s, e, "vanse_init");
+    s.t = 0;
+    s.initialized = true;
+    s.unstable = false;
+    return VANSE_OK;
+}
+
+int vanse_step(vanse_t h, int64_t n)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_step: NULL handle");
+    Solver &s = h->s;
+    if (n < 0) return fail(&s, VANSE_EINVAL, "vanse_step: n must be >= 0");
+    if (!s.initialized) return fail(&s, VANSE_ESTATE, "vanse_step: call vanse_init first");
+    if (s.unstable) return fail(&s, VANSE_EUNSTABLE, "vanse_step: solver is unstable");
+    for (int64_t k = 0; k < n; ++k) {
+        const vanse::StepArgs a = vanse::step_args(s, s.t);
+        hipError_t e = vanse::launch_step(s, a, (int)(s.t & 1));
+        if (e != hipSuccess) return hip_fail(&s, e, "vanse_step");
+        ++s.t;
+    }
+    return VANSE_OK;
+}
+
+int vanse_moments(vanse_t h, double *rho, double *p, double *u)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_moments: NULL handle");
+    Solver &s = h->s;
+    if (!s.initialized) return fail(&s, VANSE_ESTATE, "vanse_moments: call vanse_init first");
+    hipError_t e = vanse::launch_moments(s, (int)(s.t & 1), vanse::modulation(s.t, s.period),
+                                         rho, p, u);
+    if (e != hipSuccess) return hip_fail(&s, e, "vanse_moments");
+    return VANSE_OK;
+}
+
+int vanse_diagnostics(vanse_t h, double out[7])
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_diagnostics: NULL handle");
+    Solver &s = h->s;
+    if (!out) return fail(&s, VANSE_EINVAL, "vanse_diagnostics: out is NULL");
+    if (!s.initialized) return fail(&s, VANSE_ESTATE, "vanse_diagnostics: call vanse_init first");
+    double *res = s.scratch + 7 * vanse::kReduceBlocks;
+    hipError_t e = vanse::launch_diagnostics(s, (int)(s.t & 1),
+                                             vanse::modulation(s.t, s.period), res);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, res, 7 * sizeof(double), hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+    if (e != hipSuccess) return hip_fail(&s, e, "vanse_diagnostics");
+    for (int k = 0; k < 7; ++k)
+        if (!std::isfinite(out[k])) s.unstable = true;
+    if (s.unstable)
+        return fail(&s, VANSE_EUNSTABLE, "vanse_diagnostics: non-finite mass or momentum");
+    return VANSE_OK;
+}
+
+int vanse_populations(vanse_t h, double *f)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_populations: NULL handle");
+    Solver &s = h->s;
+    if (!f) return fail(&s, VANSE_EINVAL, "vanse_populations: f is NULL");
+    if (!s.initialized) return fail(&s, VANSE_ESTATE, "vanse_populations: call vanse_init first");
+    hipError_t e = vanse::launch_populations(s, (int)(s.t & 1), f);
+    if (e != hipSuccess) return hip_fail(&s, e, "vanse_populations");
+    return VANSE_OK;
+}
+
+int vanse_time(vanse_t h, int64_t *t)
+{
+    if (!h || !t) return fail(h ? &h->s : nullptr, VANSE_EINVAL, "vanse_time: NULL argument");
+    *t = h->s.t;
+    return VANSE_OK;
+}
+
+int vanse_device_bytes(vanse_t h, int64_t *bytes)
+{
+    if (!h || !bytes)
+        return fail(h ? &h->s : nullptr, VANSE_EINVAL, "vanse_device_bytes: NULL argument");
+    *bytes = (int64_t)(h->s.f_bytes + h->s.pert_bytes + h->s.scratch_bytes);
+    return VANSE_OK;
+}
+
+const char *vanse_last_error(vanse_t h)
+{
+    return h ? h->s.err.c_str() : g_create_error.c_str();
+}
+
+int vanse_lattice_info(int lattice, int *d, int *q, int *xi, double *w)
+{
+    if (lattice != VANSE_D2Q9 && lattice != VANSE_D3Q19)
+        return fail(nullptr, VANSE_EINVAL, "vanse_lattice_info: unknown lattice");
+    auto fill = [&](auto lat) {
+        using L = decltype(lat);
+        if (d) *d = L::D;
+        if (q) *q = L::Q;
+        for (int i = 0; i < L::Q; ++i) {
+            if (xi) {
+                xi[3 * i + 0] = L::cx[i];
+                xi[3 * i + 1] = L::cy[i];
+                xi[3 * i + 2] = L::cz[i];
+            }
+            if (w) w[i] = L::w[i];
+        }
+    };
+    if (lattice == VANSE_D2Q9)
+        fill(vanse::D2Q9{});
+    else
+        fill(vanse::D3Q19{});
+    return VANSE_OK;
+}
+
+int vanse_copy_probe(void *dst, const void *src, int64_t bytes, void *stream)
+{
+    if (!dst || !src || bytes <= 0 || bytes % 16)
+        return fail(nullptr, VANSE_EINVAL, "vanse_copy_probe: bad arguments");
+    hipError_t e = vanse::launch_copy_probe(dst, src, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "vanse_copy_probe");
+    return VANSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// internal.h -- solver state shared by the host API (api.hip) and the kernel
+// launchers (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace vanse {
+
+enum Mode { MODE_F64 = 0, MODE_F32S = 1, MODE_F16S = 2 };
+
+// Launch-time view of one lattice: sizes and the population plane stride
+// (elements between direction planes of the SoA population array).
+struct Geometry {
+    int nx, ny, nz;
+    int nxy;
+    int ncells;
+    long long stride;
+};
+
+// Everything one step of one solve needs, passed by value to the kernel.
+struct StepArgs {
+    Geometry geo;
+    void *f;             // populations, SoA [Q][stride], storage type of the mode
+    const void *pert;    // phi perturbation, double (FP64) or float (reduced)
+    double eps_mean;     // phi = eps_mean + m * pert
+    double m;            // modulation m(n) of the current step
+    double omega;        // 1 / tau
+    double fcoef;        // 1 - omega / 2 (Guo forcing prefactor)
+    double F[3];         // constant external force density
+    double wq;           // quadrature weight varpi_{i != 0}
+    double n2;           // 2 * (number of quadrature axes)
+    int qmask;           // quadrature axes bitmask
+};
+
+struct Solver {
+    int lattice = 0, mode = 0, d = 0, q = 0;
+    Geometry geo{};
+    double tau = 0.0;
+    double eps_mean = 1.0, period = 0.0;
+    int qmask = 0;
+    double F[3] = {0.0, 0.0, 0.0};
+    bool porosity_set = false, initialized = false, unstable = false;
+    int64_t t = 0;
+    int block = 256;             // threads per block of the step kernel
+    void *f = nullptr;           // populations
+    size_t f_bytes = 0;
+    void *pert = nullptr;        // phi perturbation (double or float)
+    size_t pert_bytes = 0;
+    double *scratch = nullptr;   // reduction partials + results
+    size_t scratch_bytes = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+constexpr int kReduceBlocks = 1024;   // fixed grid of the reduction kernels
+constexpr int kReduceThreads = 256;
+
+double modulation(int64_t n, double period);
+StepArgs step_args(const Solver &s, int64_t n);
+
+// Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_step(const Solver &s, const StepArgs &a, int parity);
+hipError_t launch_init(const Solver &s, const double *rho0, const double *u0);
+hipError_t launch_moments(const Solver &s, int parity, double m, double *rho, double *p,
+                          double *u);
+hipError_t launch_populations(const Solver &s, int parity, double *f);
+hipError_t launch_diagnostics(const Solver &s, int parity, double m, double *out_dev);
+hipError_t launch_convert_pert(const Solver &s, const double *src);
+hipError_t launch_pert_range(const Solver &s, double *out_dev);
+hipError_t launch_copy_probe(void *dst, const void *src, int64_t bytes, hipStream_t st);
+
+}  // namespace vanse

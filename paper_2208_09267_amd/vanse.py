@@ -1,0 +1,238 @@
+"""Python binding of the C ABI in ``include/vanse.h`` (ctypes, argument
+marshalling only).
+
+Every step of the VANSE lattice Boltzmann path runs in the HIP kernels of
+``libvanse.so``; this module only passes pointers of torch tensors and the
+current torch stream.  If the library is missing the import of the binding
+fails loudly: there is no CPU fallback.
+
+Low-level names mirror the C ABI (``vanse_create``, ``vanse_set_porosity``,
+``vanse_step``, ``vanse_moments`` ...).  :class:`Solver` wraps one handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch  # loads the HIP runtime the library binds to (same soname)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvanse.so")
+
+D2Q9, D3Q19 = 0, 1
+FP64, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
+DTYPES = {"fp64": FP64, "fp32_shifted": FP32_SHIFTED, "fp16_shifted": FP16_SHIFTED}
+LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19}
+
+_STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE",
+           EUNSTABLE: "EUNSTABLE"}
+
+EXPORTS = [
+    "vanse_create", "vanse_destroy", "vanse_set_stream", "vanse_set_porosity",
+    "vanse_set_force", "vanse_init", "vanse_step", "vanse_moments", "vanse_diagnostics",
+    "vanse_populations", "vanse_time", "vanse_device_bytes", "vanse_last_error",
+    "vanse_lattice_info", "vanse_copy_probe",
+]
+
+
+class VanseError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%s): %s" % (_STATUS.get(code, code), code, msg))
+        self.code = code
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load ``libvanse.so`` and declare the C signatures.  Raises if the
+    library has not been built."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise ImportError(
+                "libvanse.so not found at %s: build it with "
+                "`python -m paper_2208_09267_amd.build` (there is no CPU fallback)" % path)
+        lib = ctypes.CDLL(path)
+        P, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+        I64P = ctypes.POINTER(ctypes.c_int64)
+        sig = {
+            "vanse_create": (i, [i, I64P, d, i, ctypes.POINTER(P)]),
+            "vanse_destroy": (i, [P]),
+            "vanse_set_stream": (i, [P, P]),
+            "vanse_set_porosity": (i, [P, d, P, d, i]),
+            "vanse_set_force": (i, [P, P]),
+            "vanse_init": (i, [P, P, P]),
+            "vanse_step": (i, [P, i64]),
+            "vanse_moments": (i, [P, P, P, P]),
+            "vanse_diagnostics": (i, [P, P]),
+            "vanse_populations": (i, [P, P]),
+            "vanse_time": (i, [P, I64P]),
+            "vanse_device_bytes": (i, [P, I64P]),
+            "vanse_last_error": (ctypes.c_char_p, [P]),
+            "vanse_lattice_info": (i, [i, P, P, P, P]),
+            "vanse_copy_probe": (i, [P, P, i64, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != torch.float64:
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def lattice_info(lattice: int):
+    """(d, xi[Q][3], w[Q]) of the library's direction order."""
+    lib = load_library()
+    d, q = ctypes.c_int(), ctypes.c_int()
+    xi = (ctypes.c_int * 81)()
+    w = (ctypes.c_double * 27)()
+    rc = lib.vanse_lattice_info(lattice, ctypes.byref(d), ctypes.byref(q), xi, w)
+    if rc:
+        raise VanseError(rc, lib.vanse_last_error(None).decode())
+    Q = q.value
+    return d.value, [[xi[3 * k + a] for a in range(3)] for k in range(Q)], [w[k] for k in range(Q)]
+
+
+def copy_probe(dst: torch.Tensor, src: torch.Tensor):
+    lib = load_library()
+    n = min(dst.numel() * dst.element_size(), src.numel() * src.element_size())
+    n -= n % 16
+    rc = lib.vanse_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                              n, _stream_handle())
+    if rc:
+        raise VanseError(rc, lib.vanse_last_error(None).decode())
+
+
+class Solver:
+    """One periodic VANSE lattice Boltzmann solve on the current GPU.
+
+    ``Solver(lattice, dims, tau, dtype)`` -> ``set_porosity`` -> (``set_force``)
+    -> ``init`` -> ``step(n)`` -> ``moments()`` / ``diagnostics()``.
+    All launches go to the torch current stream at the time of the call.
+    """
+
+    def __init__(self, lattice, dims, tau, dtype=FP64):
+        self.lib = load_library()
+        if isinstance(lattice, str):
+            lattice = LATTICES[lattice]
+        if isinstance(dtype, str):
+            dtype = DTYPES[dtype]
+        dims = list(dims) + [1] * (3 - len(dims))
+        self.lattice, self.dtype, self.tau = lattice, dtype, float(tau)
+        self.dims = tuple(int(v) for v in dims)
+        self.d = 2 if lattice == D2Q9 else 3
+        self.q = 9 if lattice == D2Q9 else 19
+        self.ncells = self.dims[0] * self.dims[1] * self.dims[2]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_int64 * 3)(*self.dims)
+        rc = self.lib.vanse_create(lattice, arr, self.tau, dtype, ctypes.byref(h))
+        if rc:
+            raise VanseError(rc, self.lib.vanse_last_error(None).decode())
+        self.h = h
+
+    # -- plumbing ------------------------------------------------------
+    def _check(self, rc):
+        if rc:
+            raise VanseError(rc, self.lib.vanse_last_error(self.h).decode())
+
+    def _bind_stream(self):
+        self._check(self.lib.vanse_set_stream(self.h, _stream_handle()))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vanse_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the C ABI -------------------------------------------------------
+    def set_porosity(self, eps_mean, eps_pert=None, period=0.0, quad_axes=0):
+        self._bind_stream()
+        if eps_pert is not None:
+            eps_pert = eps_pert.to(self.device, torch.float64).contiguous().view(-1)
+            if eps_pert.numel() != self.ncells:
+                raise ValueError("eps_pert must have %d cells" % self.ncells)
+        self._check(self.lib.vanse_set_porosity(self.h, float(eps_mean), _ptr(eps_pert),
+                                                float(period), int(quad_axes)))
+
+    def set_force(self, F):
+        F = list(F) + [0.0] * (3 - len(F))
+        arr = (ctypes.c_double * 3)(*[float(v) for v in F])
+        self._check(self.lib.vanse_set_force(self.h, arr))
+
+    def init(self, rho0=None, u0=None):
+        self._bind_stream()
+        if rho0 is not None:
+            rho0 = rho0.to(self.device, torch.float64).contiguous().view(-1)
+        if u0 is not None:
+            u0 = u0.to(self.device, torch.float64).contiguous().view(self.d, self.ncells)
+        self._keep = (rho0, u0)  # alive until the init kernel has run
+        self._check(self.lib.vanse_init(self.h, _ptr(rho0), _ptr(u0)))
+
+    def step(self, n=1):
+        self._bind_stream()
+        self._check(self.lib.vanse_step(self.h, int(n)))
+
+    def moments(self):
+        """(rho[ncells], p[ncells], u[d, ncells]) as FP64 tensors at t_n."""
+        self._bind_stream()
+        rho = torch.empty(self.ncells, dtype=torch.float64, device=self.device)
+        p = torch.empty_like(rho)
+        u = torch.empty(self.d, self.ncells, dtype=torch.float64, device=self.device)
+        self._check(self.lib.vanse_moments(self.h, _ptr(rho), _ptr(p), _ptr(u)))
+        return rho, p, u
+
+    def populations(self):
+        """f_i(x, t_n) as an FP64 tensor [Q, ncells] in the library's order."""
+        self._bind_stream()
+        f = torch.empty(self.q, self.ncells, dtype=torch.float64, device=self.device)
+        self._check(self.lib.vanse_populations(self.h, _ptr(f)))
+        return f
+
+    def diagnostics(self):
+        """(mass, momentum[3], force_sum[3]); synchronises."""
+        self._bind_stream()
+        out = (ctypes.c_double * 7)()
+        self._check(self.lib.vanse_diagnostics(self.h, out))
+        return out[0], [out[1], out[2], out[3]], [out[4], out[5], out[6]]
+
+    @property
+    def time(self):
+        t = ctypes.c_int64()
+        self._check(self.lib.vanse_time(self.h, ctypes.byref(t)))
+        return t.value
+
+    @property
+    def device_bytes(self):
+        b = ctypes.c_int64()
+        self._check(self.lib.vanse_device_bytes(self.h, ctypes.byref(b)))
+        return b.value
