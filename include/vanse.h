@@ -128,6 +128,17 @@ int vanse_diagnostics(vanse_t h, double out[7]);
  * library's direction order (vanse_lattice_info).  Asynchronous. */
 int vanse_populations(vanse_t h, double *f);
 
+/* Launch shape of the step kernel.  block: threads per block, 64, 128 or
+ * 256.  flags: bitwise OR of
+ *   VANSE_TUNE_NONTEMPORAL  population loads/stores carry the nontemporal hint
+ *   VANSE_TUNE_XCD_REMAP    each XCD processes one contiguous range of blocks
+ *   VANSE_TUNE_FLAT         flattened tiling even when nx is a multiple of block
+ * Without VANSE_TUNE_FLAT a block covers `block` consecutive cells of one
+ * x-row when nx % block == 0.  Every setting computes bitwise-identical
+ * results; only speed differs.  Errors: EINVAL. */
+enum { VANSE_TUNE_NONTEMPORAL = 1, VANSE_TUNE_XCD_REMAP = 2, VANSE_TUNE_FLAT = 4 };
+int vanse_set_tuning(vanse_t h, int block, int flags);
+
 /* Current time level n (number of steps since vanse_init). */
 int vanse_time(vanse_t h, int64_t *t);
 

@@ -41,6 +41,15 @@ StepArgs step_args(const Solver &s, int64_t n)
     a.wq = quad_weight(n_axes);
     a.n2 = 2.0 * n_axes;
     a.qmask = s.qmask;
+    a.flags = s.flags;
+    a.block = (unsigned)s.block;
+    a.row = (s.allow_row && s.geo.nx % s.block == 0) ? 1 : 0;
+    a.nseg = a.row ? (unsigned)(s.geo.nx / s.block) : 1u;
+    a.nblocks = a.row ? a.nseg * (unsigned)s.geo.ny * (unsigned)s.geo.nz
+                      : (unsigned)((s.geo.ncells + s.block - 1) / s.block);
+    a.fd_nx = make_fastdiv((unsigned)s.geo.nx);
+    a.fd_ny = make_fastdiv((unsigned)s.geo.ny);
+    a.fd_seg = make_fastdiv(a.nseg);
     return a;
 }
 
@@ -292,6 +301,20 @@ int vanse_populations(vanse_t h, double *f)
     if (!s.initialized) return fail(&s, VANSE_ESTATE, "vanse_populations: call vanse_init first");
     hipError_t e = vanse::launch_populations(s, (int)(s.t & 1), f);
     if (e != hipSuccess) return hip_fail(&s, e, "vanse_populations");
+    return VANSE_OK;
+}
+
+int vanse_set_tuning(vanse_t h, int block, int flags)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_set_tuning: NULL handle");
+    Solver &s = h->s;
+    if (block != 64 && block != 128 && block != 256)
+        return fail(&s, VANSE_EINVAL, "vanse_set_tuning: block must be 64, 128 or 256");
+    if (flags & ~(VANSE_TUNE_NONTEMPORAL | VANSE_TUNE_XCD_REMAP | VANSE_TUNE_FLAT))
+        return fail(&s, VANSE_EINVAL, "vanse_set_tuning: unknown flag");
+    s.block = block;
+    s.flags = flags & (VANSE_TUNE_NONTEMPORAL | VANSE_TUNE_XCD_REMAP);
+    s.allow_row = (flags & VANSE_TUNE_FLAT) == 0;
     return VANSE_OK;
 }
 

@@ -20,6 +20,22 @@ struct Geometry {
     long long stride;
 };
 
+// Division by a launch-invariant divisor d (see fdiv in kernels.hip).
+struct FastDiv {
+    unsigned m;  // < 2^32 for every d >= 1
+    unsigned s;
+};
+
+inline FastDiv make_fastdiv(unsigned d)
+{
+    unsigned l = 0;
+    while ((1ull << l) < d) ++l;  // ceil(log2 d)
+    FastDiv f;
+    f.s = 31 + l;
+    f.m = (unsigned)(((1ull << f.s) + d - 1) / d);
+    return f;
+}
+
 // Everything one step of one solve needs, passed by value to the kernel.
 struct StepArgs {
     Geometry geo;
@@ -33,6 +49,13 @@ struct StepArgs {
     double wq;           // quadrature weight varpi_{i != 0}
     double n2;           // 2 * (number of quadrature axes)
     int qmask;           // quadrature axes bitmask
+    // launch shape
+    int row;             // 1: ROW tiling (nx % block == 0), 0: FLAT
+    int flags;           // 1: nontemporal population traffic, 2: XCD remap
+    unsigned block;      // threads per block
+    unsigned nblocks;    // grid size
+    unsigned nseg;       // ROW: blocks per x-row
+    FastDiv fd_nx, fd_ny, fd_seg;
 };
 
 struct Solver {
@@ -45,6 +68,8 @@ struct Solver {
     bool porosity_set = false, initialized = false, unstable = false;
     int64_t t = 0;
     int block = 256;             // threads per block of the step kernel
+    int flags = 0;               // step-kernel variant flags (StepArgs::flags)
+    bool allow_row = true;       // use ROW tiling when nx allows it
     void *f = nullptr;           // populations
     size_t f_bytes = 0;
     void *pert = nullptr;        // phi perturbation (double or float)

@@ -52,31 +52,69 @@ __device__ __forceinline__ R dot3(R x, R y, R z)
     return s;
 }
 
+// Storage of one population: T is the raw element type in HBM, R the
+// arithmetic type, and `shifted` / `scaled` say what the stored value v_i is:
+//   FP64        v_i = f_i                     (T = double)
+//   FP32 shift  v_i = f_i - w_i               (T = float)
+//   FP16 shift  v_i = (f_i - w_i) / w_i       (T = binary16 bits, decoded to float)
 template <int MODE> struct Storage;
-template <> struct Storage<MODE_F64> { using T = double; using R = double; };
-template <> struct Storage<MODE_F32S> { using T = float; using R = float; };
-template <> struct Storage<MODE_F16S> { using T = __half; using R = float; };
+template <> struct Storage<MODE_F64> {
+    using T = double;
+    using R = double;
+    static constexpr bool shifted = false, scaled = false;
+    static __device__ __forceinline__ R decode(T v) { return v; }
+    static __device__ __forceinline__ T encode(R v) { return v; }
+};
+template <> struct Storage<MODE_F32S> {
+    using T = float;
+    using R = float;
+    static constexpr bool shifted = true, scaled = false;
+    static __device__ __forceinline__ R decode(T v) { return v; }
+    static __device__ __forceinline__ T encode(R v) { return v; }
+};
+template <> struct Storage<MODE_F16S> {
+    using T = unsigned short;
+    using R = float;
+    static constexpr bool shifted = true, scaled = true;
+    static __device__ __forceinline__ R decode(T v) { return __half2float(__ushort_as_half(v)); }
+    static __device__ __forceinline__ T encode(R v) { return __half_as_ushort(__float2half_rn(v)); }
+};
 
-// Decode a stored population into the arithmetic type: f_i itself (FP64), or
-// the deviation g_i = f_i - w_i (shifted modes; FP16 stores g_i / w_i).
+// FP64 value of f_i from a stored population (off the hot path).
 template <class L, int MODE, int I>
-__device__ __forceinline__ typename Storage<MODE>::R decode(typename Storage<MODE>::T v)
+__device__ __forceinline__ double to_f64(typename Storage<MODE>::T raw)
 {
-    if constexpr (MODE == MODE_F16S)
-        return float(L::w[I]) * __half2float(v);
-    else
-        return v;
+    using St = Storage<MODE>;
+    const double v = double(St::decode(raw));
+    if constexpr (!St::shifted) return v;
+    else if constexpr (!St::scaled) return L::w[I] + v;
+    else return L::w[I] + L::w[I] * v;
 }
 
-template <class L, int MODE, int I>
-__device__ __forceinline__ typename Storage<MODE>::T encode(typename Storage<MODE>::R v)
+// Unsigned division by a launch-invariant divisor d >= 1 for dividends
+// n < 2^31: q = (n * m) >> s with s = 31 + ceil(log2 d), m = ceil(2^s / d)
+// (the round-up multiplier of Granlund and Montgomery, 1994).
+__device__ __forceinline__ unsigned fdiv(unsigned n, const FastDiv &f)
 {
-    if constexpr (MODE == MODE_F16S) {
-        constexpr float inv_w = float(1.0 / L::w[I]);
-        return __float2half_rn(v * inv_w);
-    } else {
-        return v;
-    }
+    return (unsigned)(((unsigned long long)n * f.m) >> f.s);
+}
+
+// Global memory access at a 32-bit byte offset from a base pointer.  With a
+// wave-uniform base the compiler emits the scalar-base (saddr) form, so a
+// lane carries one 32-bit offset instead of a 64-bit address.
+template <class T, bool NT>
+__device__ __forceinline__ T ld(const T *base, unsigned byte_off)
+{
+    const T *p = reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <class T, bool NT>
+__device__ __forceinline__ void st(T *base, unsigned byte_off, T v)
+{
+    T *p = reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -117,129 +155,227 @@ __device__ __forceinline__ Cell locate(const Geometry &g, int c)
 //       (cell integral, eqs. quad / latDiffRuleIIre, Table 3)
 //   g = (phi(x+e) - phi(x-e)) / 2  (central-difference gradient of the
 //       pressure-correction force)
+// e[] holds phi at x, x+ex, x-ex, x+ey, x-ey, x+ez, x-ez.
+template <class L, class R>
+__device__ __forceinline__ void eps_combine(const R (&e)[7], R wq, R n2, int qmask, R &I,
+                                            R &gx, R &gy, R &gz)
+{
+    R S = R(0);
+    if (qmask & 1) {
+        S = S + e[1];
+        S = S + e[2];
+    }
+    if (qmask & 2) {
+        S = S + e[3];
+        S = S + e[4];
+    }
+    if constexpr (L::D == 3) {
+        if (qmask & 4) {
+            S = S + e[5];
+            S = S + e[6];
+        }
+    }
+    I = e[0] + wq * (S - n2 * e[0]);
+    gx = R(0.5) * (e[1] - e[2]);
+    gy = R(0.5) * (e[3] - e[4]);
+    gz = (L::D == 3) ? R(0.5) * (e[5] - e[6]) : R(0);
+}
+
 template <class L, class R>
 __device__ __forceinline__ void eps_ops(const R *__restrict__ pert, R eps_mean, R m, R wq,
                                         R n2, int qmask, const Cell &k, R &I, R &gx, R &gy,
                                         R &gz)
 {
-    const R e0 = eps_mean + m * pert[k.c];
-    const R xp = eps_mean + m * pert[k.at(1, 0, 0)];
-    const R xm = eps_mean + m * pert[k.at(-1, 0, 0)];
-    const R yp = eps_mean + m * pert[k.at(0, 1, 0)];
-    const R ym = eps_mean + m * pert[k.at(0, -1, 0)];
-    R zp = R(0), zm = R(0);
+    R e[7];
+    e[0] = eps_mean + m * pert[k.c];
+    e[1] = eps_mean + m * pert[k.at(1, 0, 0)];
+    e[2] = eps_mean + m * pert[k.at(-1, 0, 0)];
+    e[3] = eps_mean + m * pert[k.at(0, 1, 0)];
+    e[4] = eps_mean + m * pert[k.at(0, -1, 0)];
+    e[5] = e[6] = R(0);
     if constexpr (L::D == 3) {
-        zp = eps_mean + m * pert[k.at(0, 0, 1)];
-        zm = eps_mean + m * pert[k.at(0, 0, -1)];
+        e[5] = eps_mean + m * pert[k.at(0, 0, 1)];
+        e[6] = eps_mean + m * pert[k.at(0, 0, -1)];
     }
-    R S = R(0);
-    if (qmask & 1) {
-        S = S + xp;
-        S = S + xm;
-    }
-    if (qmask & 2) {
-        S = S + yp;
-        S = S + ym;
-    }
-    if constexpr (L::D == 3) {
-        if (qmask & 4) {
-            S = S + zp;
-            S = S + zm;
-        }
-    }
-    I = e0 + wq * (S - n2 * e0);
-    gx = R(0.5) * (xp - xm);
-    gy = R(0.5) * (yp - ym);
-    gz = (L::D == 3) ? R(0.5) * (zp - zm) : R(0);
+    eps_combine<L, R>(e, wq, n2, qmask, I, gx, gy, gz);
 }
 
 // ---------------------------------------------------------------------------
-// BGK collision with Guo forcing of one cell, in place on v[Q].
-//   FP64:    v holds f_i; M0 = sum f.
-//   shifted: v holds g_i = f_i - w_i; M0 = 1 + sum g (sum w = 1, sum w xi = 0),
-//            and the equilibrium deviation f^eq_i - w_i =
-//            w_i (dM0 + M0 (3 cu + 9/2 cu^2 - 3/2 uu)) keeps every stored and
-//            relaxed quantity small.
+// BGK collision with Guo forcing of one cell, in place on the stored values
+// v[Q] (f_i, f_i - w_i, or (f_i - w_i)/w_i by storage mode).
+//
+// Per cell: M0 = sum f (= 1 + sum (f - w) in the shifted modes, since
+// sum w = 1 and sum w xi = 0), rho = M0/I (eq. density), p = rho/3,
+// F = p grad(phi) + F_ext (eq. pressForce), u = (j + F/2)/M0 (eq. velocity).
+// The update f - (f - f^eq)/tau + Omega^F (eq. lbe with eq. feq, rho I = M0,
+// and Guo's forcing term) is evaluated for each pair of opposite directions
+// +-xi, whose equilibrium and forcing terms split into a part even in xi
+// and a part odd in xi:
+//   v'_{+-} = (1 - omega) v_{+-} + W [P0 + cu (a45 cu + b9 cF)]
+//                                 +- W [c3 cu + d3 cF]
+// with cu = xi.u, cF = xi.F, P0 = omega E - 3 k uF, a45 = 9/2 omega M0,
+// b9 = 9 k, c3 = 3 omega M0, d3 = 3 k, k = 1 - omega/2, W = w_i (or 1 when
+// the stored value is scaled by 1/w_i), and E = M0 (1 - 3/2 uu) for f, or
+// dM0 - 3/2 uu M0 for the shifted values.
 template <class L, int MODE, class R>
 __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R omega,
                                         R fcoef, R Fex, R Fey, R Fez)
 {
-    constexpr bool shifted = (MODE != MODE_F64);
-    R s0 = R(0), jx = R(0), jy = R(0), jz = R(0);
-    static_for<0, L::Q>([&](auto ic) {
+    using St = Storage<MODE>;
+    constexpr int H = L::H;
+    R s0, jx = R(0), jy = R(0), jz = R(0);
+    if constexpr (St::scaled)
+        s0 = R(L::w[0]) * v[0];
+    else
+        s0 = v[0];
+    static_for<1, H + 1>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        s0 = s0 + v[i];
-        if constexpr (L::cx[i] == 1) jx = jx + v[i];
-        if constexpr (L::cx[i] == -1) jx = jx - v[i];
-        if constexpr (L::cy[i] == 1) jy = jy + v[i];
-        if constexpr (L::cy[i] == -1) jy = jy - v[i];
-        if constexpr (L::cz[i] == 1) jz = jz + v[i];
-        if constexpr (L::cz[i] == -1) jz = jz - v[i];
+        constexpr int o = i + H;
+        const R sp = v[i] + v[o];
+        const R dm = v[i] - v[o];
+        constexpr R w = St::scaled ? R(L::w[i]) : R(1);
+        s0 = s0 + w * sp;
+        if constexpr (L::cx[i] != 0) jx = jx + R(L::cx[i]) * w * dm;
+        if constexpr (L::cy[i] != 0) jy = jy + R(L::cy[i]) * w * dm;
+        if constexpr (L::cz[i] != 0) jz = jz + R(L::cz[i]) * w * dm;
     });
-    const R M0 = shifted ? R(1) + s0 : s0;
+    const R M0 = St::shifted ? R(1) + s0 : s0;
     const R rho = M0 / I;               // eq. density
-    const R p = rho / R(3);             // p = rho c_s^2
+    const R p = rho * R(1.0 / 3.0);     // p = rho c_s^2
     const R Fx = p * gx + Fex;          // F_PC + F_ext (eq. pressForce)
     const R Fy = p * gy + Fey;
     const R Fz = (L::D == 3) ? p * gz + Fez : R(0);
-    const R ux = (jx + R(0.5) * Fx) / M0;  // eq. velocity
-    const R uy = (jy + R(0.5) * Fy) / M0;
-    const R uz = (L::D == 3) ? (jz + R(0.5) * Fz) / M0 : R(0);
+    const R inv = R(1) / M0;
+    const R ux = (jx + R(0.5) * Fx) * inv;  // eq. velocity
+    const R uy = (jy + R(0.5) * Fy) * inv;
+    const R uz = (L::D == 3) ? (jz + R(0.5) * Fz) * inv : R(0);
     const R uu = ux * ux + uy * uy + uz * uz;
     const R uF = ux * Fx + uy * Fy + uz * Fz;
-    static_for<0, L::Q>([&](auto ic) {
+
+    const R om1 = R(1) - omega;
+    const R E = St::shifted ? s0 - R(1.5) * uu * M0 : M0 * (R(1) - R(1.5) * uu);
+    const R P0 = omega * E - R(3) * fcoef * uF;
+    const R a45 = R(4.5) * omega * M0;
+    const R b9 = R(9) * fcoef;
+    const R c3 = R(3) * omega * M0;
+    const R d3 = R(3) * fcoef;
+    {
+        constexpr R W0 = St::scaled ? R(1) : R(L::w[0]);
+        v[0] = om1 * v[0] + W0 * P0;
+    }
+    static_for<1, H + 1>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        constexpr R w = R(L::w[i]);
+        constexpr int o = i + H;
+        constexpr R W = St::scaled ? R(1) : R(L::w[i]);
         const R cu = dot3<L::cx[i], L::cy[i], L::cz[i]>(ux, uy, uz);
         const R cF = dot3<L::cx[i], L::cy[i], L::cz[i]>(Fx, Fy, Fz);
-        const R poly = R(3) * cu + R(4.5) * cu * cu - R(1.5) * uu;
-        R feq;
-        if constexpr (shifted)
-            feq = w * (s0 + M0 * poly);
-        else
-            feq = w * M0 * (R(1) + poly);
-        const R om = fcoef * w * (R(3) * cF - R(3) * uF + R(9) * cu * cF);
-        v[i] = v[i] - omega * (v[i] - feq) + om;
+        const R sym = W * (P0 + cu * (a45 * cu + b9 * cF));
+        const R anti = W * (c3 * cu + d3 * cF);
+        v[i] = om1 * v[i] + sym + anti;
+        v[o] = om1 * v[o] + sym - anti;
     });
 }
 
 // ---------------------------------------------------------------------------
-// One fused time step (the hot path): phi stencil, Q loads, collision,
-// Q stores, for one cell per thread.
-template <class L, int MODE, int PARITY>
+// One fused time step (the hot path): Q population loads, the phi stencil,
+// the collision and Q stores for one cell per thread.
+//
+// ROW tiling (nx a multiple of the block size B): a block covers B
+// consecutive cells of one x-row, so the y/z neighbour rows are
+// wave-uniform; every access is a scalar row base plus a 32-bit lane offset
+// of x-1, x or x+1.  FLAT tiling (any size): the lattice is flattened and
+// divided with launch-invariant multipliers.
+// XCD remap (flags & 2): the hardware deals blocks round-robin over the 8
+// XCDs; the remap gives each XCD one contiguous range of blocks, so lines
+// shared by neighbouring blocks (shifted x accesses, phi neighbour rows) meet
+// in the same L2.
+template <class L, int MODE, int PARITY, bool ROW, bool NT>
 __global__ void __launch_bounds__(256) step_kernel(StepArgs a)
 {
-    using T = typename Storage<MODE>::T;
-    using R = typename Storage<MODE>::R;
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= a.geo.ncells) return;
-    const Cell k = locate(a.geo, c);
-    R I, gx, gy, gz;
-    eps_ops<L, R>(static_cast<const R *>(a.pert), R(a.eps_mean), R(a.m), R(a.wq), R(a.n2),
-                  a.qmask, k, I, gx, gy, gz);
+    using St = Storage<MODE>;
+    using T = typename St::T;
+    using R = typename St::R;
+
+    unsigned b = blockIdx.x;
+    if (a.flags & 2) {
+        const unsigned q = a.nblocks >> 3, r = a.nblocks & 7, xcd = b & 7, idx = b >> 3;
+        b = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+    }
+    int x, y, z;
+    if constexpr (ROW) {
+        const unsigned row = fdiv(b, a.fd_seg);
+        const unsigned seg = b - row * a.nseg;
+        z = (int)fdiv(row, a.fd_ny);
+        y = (int)row - z * a.geo.ny;
+        x = (int)(seg * a.block + threadIdx.x);
+    } else {
+        const unsigned c = b * a.block + threadIdx.x;
+        if (c >= (unsigned)a.geo.ncells) return;
+        const unsigned yz = fdiv(c, a.fd_nx);
+        x = (int)(c - yz * a.geo.nx);
+        z = (int)fdiv(yz, a.fd_ny);
+        y = (int)yz - z * a.geo.ny;
+    }
+    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
+    const int X[3] = {(x == 0 ? nx : x) - 1, x, (x + 1 == nx) ? 0 : x + 1};
+    const int Yo[3] = {((y == 0 ? ny : y) - 1) * nx, y * nx, ((y + 1 == ny) ? 0 : y + 1) * nx};
+    const int Zo[3] = {((z == 0 ? nz : z) - 1) * a.geo.nxy, z * a.geo.nxy,
+                       ((z + 1 == nz) ? 0 : z + 1) * a.geo.nxy};
+
+    // element at offset (dx, dy, dz) of plane p: row base + lane offset
+    auto load = [&](const T *plane, int dx, int dy, int dz) -> T {
+        if constexpr (ROW)
+            return ld<T, NT>(plane + (Zo[dz + 1] + Yo[dy + 1]),
+                             (unsigned)X[dx + 1] * (unsigned)sizeof(T));
+        else
+            return ld<T, NT>(plane, (unsigned)(Zo[dz + 1] + Yo[dy + 1] + X[dx + 1]) *
+                                        (unsigned)sizeof(T));
+    };
+    auto store = [&](T *plane, int dx, int dy, int dz, T val) {
+        if constexpr (ROW)
+            st<T, NT>(plane + (Zo[dz + 1] + Yo[dy + 1]),
+                      (unsigned)X[dx + 1] * (unsigned)sizeof(T), val);
+        else
+            st<T, NT>(plane, (unsigned)(Zo[dz + 1] + Yo[dy + 1] + X[dx + 1]) *
+                                 (unsigned)sizeof(T), val);
+    };
 
     T *__restrict__ f = static_cast<T *>(a.f);
     const long long S = a.geo.stride;
     R v[L::Q];
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        if constexpr (PARITY == 0) {
-            v[i] = decode<L, MODE, i>(f[i * S + c]);
-        } else {
-            constexpr int o = opp<L>(i);
-            v[i] = decode<L, MODE, i>(f[o * S + k.at(-L::cx[i], -L::cy[i], -L::cz[i])]);
-        }
+        if constexpr (PARITY == 0)
+            v[i] = St::decode(load(f + i * S, 0, 0, 0));
+        else
+            v[i] = St::decode(load(f + opp<L>(i) * S, -L::cx[i], -L::cy[i], -L::cz[i]));
     });
+
+    const R *__restrict__ pert = static_cast<const R *>(a.pert);
+    const R em = R(a.eps_mean), mm = R(a.m);
+    R e[7];
+    e[0] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[1] * sizeof(R));
+    e[1] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[2] * sizeof(R));
+    e[2] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[0] * sizeof(R));
+    e[3] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[2]), (unsigned)X[1] * sizeof(R));
+    e[4] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[0]), (unsigned)X[1] * sizeof(R));
+    e[5] = e[6] = R(0);
+    if constexpr (L::D == 3) {
+        e[5] = em + mm * ld<R, false>(pert + (Zo[2] + Yo[1]), (unsigned)X[1] * sizeof(R));
+        e[6] = em + mm * ld<R, false>(pert + (Zo[0] + Yo[1]), (unsigned)X[1] * sizeof(R));
+    }
+    R I, gx, gy, gz;
+    eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
+
     collide<L, MODE, R>(v, I, gx, gy, gz, R(a.omega), R(a.fcoef), R(a.F[0]), R(a.F[1]),
                         R(a.F[2]));
+
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        if constexpr (PARITY == 0) {
-            constexpr int o = opp<L>(i);
-            f[o * S + c] = encode<L, MODE, i>(v[i]);
-        } else {
-            f[i * S + k.at(L::cx[i], L::cy[i], L::cz[i])] = encode<L, MODE, i>(v[i]);
-        }
+        if constexpr (PARITY == 0)
+            store(f + opp<L>(i) * S, 0, 0, 0, St::encode(v[i]));
+        else
+            store(f + i * S, L::cx[i], L::cy[i], L::cz[i], St::encode(v[i]));
     });
 }
 
@@ -262,11 +398,7 @@ __device__ __forceinline__ void load_natural(const StepArgs &a, const Cell &k, i
             raw = f[i * S + k.c];
         else
             raw = f[opp<L>(i) * S + k.at(-L::cx[i], -L::cy[i], -L::cz[i])];
-        const R val = decode<L, MODE, i>(raw);
-        if constexpr (MODE == MODE_F64)
-            fo[i] = val;
-        else
-            fo[i] = L::w[i] + double(val);
+        fo[i] = to_f64<L, MODE, i>(raw);
     });
 }
 
@@ -357,10 +489,12 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double *__r
         constexpr int i = decltype(ic)::value;
         const double cu = L::cx[i] * u[0] + L::cy[i] * u[1] + L::cz[i] * u[2];
         const double feq = L::w[i] * M0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-        if constexpr (MODE == MODE_F64)
+        if constexpr (!Storage<MODE>::shifted)
             f[i * a.geo.stride + c] = feq;
+        else if constexpr (!Storage<MODE>::scaled)
+            f[i * a.geo.stride + c] = Storage<MODE>::encode(R(feq - L::w[i]));
         else
-            f[i * a.geo.stride + c] = encode<L, MODE, i>(R(feq - L::w[i]));
+            f[i * a.geo.stride + c] = Storage<MODE>::encode(R((feq - L::w[i]) / L::w[i]));
     });
 }
 
@@ -492,14 +626,24 @@ static hipError_t dispatch(int lattice, int mode, Fn &&fn)
 
 hipError_t launch_step(const Solver &s, const StepArgs &a, int parity)
 {
-    const unsigned nb = blocks_for(a.geo.ncells, s.block);
+    const bool nt = (a.flags & 1) != 0;
     return dispatch(s.lattice, s.mode, [&](auto lat, auto mode) {
         using L = decltype(lat);
         constexpr int M = decltype(mode)::value;
-        if (parity == 0)
-            step_kernel<L, M, 0><<<nb, s.block, 0, s.stream>>>(a);
+        auto go = [&](auto row_c, auto nt_c) {
+            constexpr bool ROW = decltype(row_c)::value;
+            constexpr bool NT = decltype(nt_c)::value;
+            if (parity == 0)
+                step_kernel<L, M, 0, ROW, NT><<<a.nblocks, a.block, 0, s.stream>>>(a);
+            else
+                step_kernel<L, M, 1, ROW, NT><<<a.nblocks, a.block, 0, s.stream>>>(a);
+        };
+        using T_ = std::true_type;
+        using F_ = std::false_type;
+        if (a.row)
+            nt ? go(T_{}, T_{}) : go(T_{}, F_{});
         else
-            step_kernel<L, M, 1><<<nb, s.block, 0, s.stream>>>(a);
+            nt ? go(F_{}, T_{}) : go(F_{}, F_{});
         return hipGetLastError();
     });
 }

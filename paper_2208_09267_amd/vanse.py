@@ -33,8 +33,9 @@ EXPORTS = [
     "vanse_create", "vanse_destroy", "vanse_set_stream", "vanse_set_porosity",
     "vanse_set_force", "vanse_init", "vanse_step", "vanse_moments", "vanse_diagnostics",
     "vanse_populations", "vanse_time", "vanse_device_bytes", "vanse_last_error",
-    "vanse_lattice_info", "vanse_copy_probe",
+    "vanse_lattice_info", "vanse_copy_probe", "vanse_set_tuning",
 ]
+TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT = 1, 2, 4
 
 
 class VanseError(RuntimeError):
@@ -77,6 +78,7 @@ def load_library(path: str = LIB_PATH):
             "vanse_last_error": (ctypes.c_char_p, [P]),
             "vanse_lattice_info": (i, [i, P, P, P, P]),
             "vanse_copy_probe": (i, [P, P, i64, P]),
+            "vanse_set_tuning": (i, [P, i, i]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -183,6 +185,11 @@ class Solver:
                 raise ValueError("eps_pert must have %d cells" % self.ncells)
         self._check(self.lib.vanse_set_porosity(self.h, float(eps_mean), _ptr(eps_pert),
                                                 float(period), int(quad_axes)))
+
+    def set_tuning(self, block=256, flags=0):
+        """Threads per block (64/128/256) and TUNE_* flags of the step kernel;
+        results are bitwise identical for every setting."""
+        self._check(self.lib.vanse_set_tuning(self.h, int(block), int(flags)))
 
     def set_force(self, F):
         F = list(F) + [0.0] * (3 - len(F))

@@ -168,3 +168,24 @@ def test_device_side_validation_and_state_errors():
     s.step(2)
     assert s.time == 2
     s.close()
+
+
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+def test_every_launch_shape_is_bitwise_identical(dtype):
+    dims = (128, 6, 5)  # nx a multiple of every block size: ROW and FLAT both reachable
+    pert = W.fourier_eps(dims, seed=9)
+    u0 = torch.from_numpy(np.ascontiguousarray(W.taylor_green(dims, 0.02))).cuda()
+    ref = None
+    for block in (64, 128, 256):
+        for flags in (0, 1, 2, 3, 4, 6):
+            s = vanse.Solver("D3Q19", dims, 0.57, dtype)
+            s.set_tuning(block, flags)
+            s.set_porosity(0.75, torch.from_numpy(pert).cuda(), 40.0)
+            s.set_force((1e-6, 0.0, -2e-6))
+            s.init(None, u0)
+            s.step(13)
+            f = s.populations().cpu().numpy()
+            s.close()
+            if ref is None:
+                ref = f
+            assert np.array_equal(f, ref), (block, flags)
