@@ -89,6 +89,134 @@ def gpu_variant(variant, w, pert_t, u0_t, steps, warmup):
             "mass": mass}
 
 
+def batched_run(steps=500, trial=5):
+    """64 independent D3Q19 solves (edges 32/48/64/96, tau in [0.55, 1],
+    own seeded phi each), FP32 shifted, advanced together by the batched
+    launch; the launch shape comes from the autotuner, whose trial steps are
+    real steps and are included in the run.  Returns aggregate throughput of
+    the steps after tuning."""
+    import numpy as np
+    import torch
+
+    from paper_2208_09267_amd import vanse
+    from paper_2208_09267_amd import workloads as W
+
+    ws = W.batched_64()
+    dev = torch.device("cuda", 0)
+    solvers = []
+    for w in ws:
+        s = vanse.Solver(w.lattice, w.dims, w.tau, vanse.FP32_SHIFTED)
+        s.set_porosity(w.eps_mean, torch.from_numpy(w.eps_pert()).to(dev), w.period)
+        s.init(None, torch.from_numpy(np.ascontiguousarray(w.u0())).to(dev))
+        solvers.append(s)
+    b = vanse.Batch(solvers)
+    block, flags, run = b.autotune(trial)
+    timed = steps - run
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(timed)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = sum(w.ncells for w in ws)
+    assert all(s.time == steps for s in solvers)
+    b.close()
+    for s in solvers:
+        s.close()
+    gbs = BYTES_PER_LUP["fp32_shifted"] * cells * timed / (ms / 1e3) / 1e9
+    return {"workload": "64 D3Q19 solves, edges uniform in {32,48,64,96}, tau U[0.55,1.0], "
+                        "seeded phi per solve, FP32 shifted, %d steps each" % steps,
+            "total_cells": cells, "steps_timed": timed, "autotune_steps": run,
+            "launch": {"block": block, "nontemporal": bool(flags & 1), "graph_chunk": 16},
+            "mlups": round(cells * timed / (ms / 1e3) / 1e6, 1),
+            "ms_per_step": round(ms / timed, 5), "gb_s": round(gbs, 1),
+            "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+
+
+def _solve_fields(w, dtype, progress=None):
+    """Run workload w for w.steps steps in the given storage mode and return
+    (rho, p, u) as FP64 CUDA tensors."""
+    import numpy as np
+    import torch
+
+    from paper_2208_09267_amd import vanse
+
+    dev = torch.device("cuda", 0)
+    s = vanse.Solver(w.lattice, w.dims, w.tau, dtype)
+    s.set_porosity(w.eps_mean, torch.from_numpy(w.eps_pert()).to(dev), w.period)
+    s.init(None, torch.from_numpy(np.ascontiguousarray(w.u0())).to(dev))
+    done = 0
+    while done < w.steps:
+        k = min(1000, w.steps - done)
+        s.step(k)
+        done += k
+        if progress:
+            torch.cuda.synchronize()
+            print("# %s: %d/%d steps" % (progress, done, w.steps), file=sys.stderr, flush=True)
+    rho, p, u = s.moments()
+    torch.cuda.synchronize()
+    s.close()
+    return rho, p, u
+
+
+def precision_study():
+    """Error of the FP32- and FP16-shifted storage modes against the FP64
+    path (which matches the CPU oracle to <= 1e-11) on the D3Q19 256^3
+    workload after 2000 steps, next to the FP64 discretisation error at the
+    same resolution, estimated against a 512^3 FP64 run of the same physical
+    problem under diffusive scaling (tau fixed, dt ~ dx^2: 8000 steps, phi
+    period 4000 steps, Taylor-Green amplitude 0.01; u compared as u_256 vs
+    2 u_512, rho and p deviations from their means as q_256 vs 4 q_512, at
+    the coincident nodes)."""
+    import dataclasses
+
+    import torch
+
+    from paper_2208_09267_amd import vanse
+    from paper_2208_09267_amd import workloads as W
+
+    w = W.d3q19_256()
+    n = w.dims[0]
+    ref = {}
+    for name, dt in (("fp64", vanse.FP64), ("fp32_shifted", vanse.FP32_SHIFTED),
+                     ("fp16_shifted", vanse.FP16_SHIFTED)):
+        ref[name] = _solve_fields(w, dt, progress=name)
+    w2 = dataclasses.replace(w, name="D3Q19 512^3 reference", dims=(2 * n,) * 3,
+                             steps=4 * w.steps, period=4 * w.period, tgv_amp=w.tgv_amp / 2)
+    r2, p2, u2 = _solve_fields(w2, vanse.FP64, progress="fp64 512^3")
+
+    def inject(a, comps=None):
+        g = a.view(-1, 2 * n, 2 * n, 2 * n) if comps else a.view(2 * n, 2 * n, 2 * n)
+        g = g[..., ::2, ::2, ::2]
+        return g.reshape(comps, -1) if comps else g.reshape(-1)
+
+    r64, p64, u64 = ref["fp64"]
+    disc = {"rho": (r64 - r64.mean()) - 4.0 * (inject(r2) - r2.mean()),
+            "p": (p64 - p64.mean()) - 4.0 * (inject(p2) - p2.mean()),
+            "u": (u64 - 2.0 * inject(u2, 3)).norm(dim=0)}
+    del r2, p2, u2
+
+    def norms(d):
+        return {"L2": float(d.pow(2).mean().sqrt()), "Linf": float(d.abs().max())}
+
+    out = {"workload": w.name, "steps": w.steps,
+           "reference": "GPU FP64 (matches the CPU oracle to <= 1e-11 relative Linf)",
+           "discretisation": {k: norms(v) for k, v in disc.items()}, "modes": {}}
+    for name in ("fp32_shifted", "fp16_shifted"):
+        r, p, u = ref[name]
+        err = {"rho": r - r64, "p": p - p64, "u": (u - u64).norm(dim=0),
+               "p_meanfree": (p - p.mean()) - (p64 - p64.mean())}
+        e = {k: norms(v) for k, v in err.items()}
+        ratio = {}
+        for k in ("rho", "p", "u"):
+            dk = out["discretisation"][k]
+            src = e["p_meanfree"] if k == "p" else e[k]
+            ratio[k] = {nn: src[nn] / dk[nn] for nn in ("L2", "Linf")}
+        out["modes"][name] = {"error_vs_fp64": e, "ratio_to_discretisation_error": ratio}
+    return out
+
+
 def cpu_baseline(w, pert, u0, seconds):
     """The CPU oracle (FP64, as it stands) on the same workload, timed for a
     bounded number of steps."""
@@ -120,6 +248,9 @@ def main():
                     help="comma list; the first one is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--precision", action="store_true",
+                    help="run the FP32/FP16 error study instead of the throughput bench")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -132,6 +263,11 @@ def main():
     import torch
 
     from paper_2208_09267_amd import workloads as W
+
+    if args.precision:
+        torch.cuda.set_device(0)
+        print(json.dumps({"precision": precision_study()}), flush=True)
+        return
 
     w = W.d3q19_256()
     pert = w.eps_pert()
@@ -178,6 +314,9 @@ def main():
                          "gb_s": round(x["gb_s"], 1), "frac_hbm": round(x["frac_hbm"], 4),
                          "bytes_per_lup": x["bytes_per_lup"]} for v, x in results.items()},
     }
+    if not args.no_batched:
+        out["batched"] = batched_run()
+        print("# batched: %s" % json.dumps(out["batched"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, pert, u0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -139,6 +139,48 @@ int vanse_populations(vanse_t h, double *f);
 enum { VANSE_TUNE_NONTEMPORAL = 1, VANSE_TUNE_XCD_REMAP = 2, VANSE_TUNE_FLAT = 4 };
 int vanse_set_tuning(vanse_t h, int block, int flags);
 
+/* ---------------------------------------------------------------------------
+ * Batched stepping: many independent solves advanced by one kernel launch per
+ * time step.  The grid is a flattened table of blocks in which each solve owns
+ * a contiguous range; each solve keeps its own size, tau, phi, force and time
+ * level (and so its own AA parity).  The per-cell arithmetic is the same as
+ * vanse_step's, so a solve evolves bitwise identically alone and in a batch.
+ * Steps are issued in chunks; a full chunk replays a captured hipGraph. */
+typedef struct vanse_batch *vanse_batch_t;
+
+/* Create a batch over `count` >= 1 distinct, initialised solvers that share
+ * lattice and dtype (host array of handles).  The batch does not own them:
+ * they must outlive it and must not be stepped by vanse_step while it
+ * exists.  Allocates small device tables (hipMalloc).  Errors: EINVAL,
+ * ESTATE, ENOMEM, EDEVICE. */
+int vanse_batch_create(const vanse_t *solvers, int count, vanse_batch_t *out);
+
+/* Free the batch's tables and graph (not the solvers).  b may be NULL. */
+int vanse_batch_destroy(vanse_batch_t b);
+
+/* Launch later work of b on stream (NULL = null stream). */
+int vanse_batch_set_stream(vanse_batch_t b, void *stream);
+
+/* Threads per block (64, 128, 256) and flags (VANSE_TUNE_NONTEMPORAL only)
+ * of the batched kernel; chunk = steps per captured graph (0: no graph,
+ * per-step launches).  Results do not depend on any of these. */
+int vanse_batch_set_tuning(vanse_batch_t b, int block, int flags, int chunk);
+
+/* Advance every member n >= 0 steps (asynchronous).  Errors: EINVAL,
+ * EUNSTABLE (a member is unstable), EDEVICE. */
+int vanse_batch_step(vanse_batch_t b, int64_t n);
+
+/* Autotune the batched launch shape: each candidate (block, flags) runs
+ * `steps_per_trial` REAL steps of the batch, timed with HIP events, and the
+ * fastest is kept and cached for batches of the same lattice, dtype and
+ * size class.  Members advance 6 * steps_per_trial steps (0 if the choice
+ * came from the cache; *steps_run tells).  Synchronises. */
+int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *flags,
+                         int64_t *steps_run);
+
+/* Last error message of b (NULL: of the last failed vanse_batch_create). */
+const char *vanse_batch_last_error(vanse_batch_t b);
+
 /* Current time level n (number of steps since vanse_init). */
 int vanse_time(vanse_t h, int64_t *t);
 

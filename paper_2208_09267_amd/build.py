@@ -18,6 +18,9 @@ ARCH = "gfx950"
 # without them, so hipcc emits scalar-per-lane FP32 arithmetic only.
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    # contract a*b+c only within one source expression, so a device function
+    # compiles to the same arithmetic in every kernel that inlines it
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]

@@ -2,11 +2,16 @@
 // validation, ownership of device memory, time stepping and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "../../include/vanse.h"
 #include "internal.h"
@@ -14,6 +19,25 @@
 
 struct vanse_solver {
     vanse::Solver s;
+};
+
+struct vanse_batch {
+    std::vector<vanse_t> members;
+    int lattice = 0, mode = 0, count = 0;
+    int block = 256;
+    bool nt = false;
+    int chunk = 16;                     // steps per captured graph; 0 = no graph
+    unsigned nblocks = 0;
+    vanse::BatchMember *d_members = nullptr;
+    unsigned *d_owner = nullptr;
+    char *d_tab = nullptr;              // [chunk_cap][count] m values, then [count] t0
+    char *h_tab[2] = {nullptr, nullptr};  // pinned staging, double buffered
+    hipEvent_t tab_done[2] = {nullptr, nullptr};
+    int cur = 0;
+    int chunk_cap = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
 };
 
 namespace vanse {
@@ -369,6 +393,318 @@ int vanse_copy_probe(void *dst, const void *src, int64_t bytes, void *stream)
     hipError_t e = vanse::launch_copy_probe(dst, src, bytes, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(nullptr, e, "vanse_copy_probe");
     return VANSE_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched stepping.
+namespace {
+
+thread_local std::string g_batch_error;
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune_cache;  // (lat, mode, log2 cells)
+
+int bfail(vanse_batch *b, int code, const std::string &msg)
+{
+    if (b)
+        b->err = msg;
+    else
+        g_batch_error = msg;
+    return code;
+}
+
+void batch_free(vanse_batch *b)
+{
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    for (int k = 0; k < 2; ++k) {
+        if (b->tab_done[k]) (void)hipEventDestroy(b->tab_done[k]);
+        if (b->h_tab[k]) (void)hipHostFree(b->h_tab[k]);
+    }
+    (void)hipFree(b->d_members);
+    (void)hipFree(b->d_owner);
+    (void)hipFree(b->d_tab);
+}
+
+size_t tab_bytes(const vanse_batch *b)
+{
+    return sizeof(double) * (size_t)b->chunk_cap * b->count + sizeof(long long) * b->count;
+}
+
+// (Re)build the member and owner tables for the current block size.
+int batch_layout(vanse_batch *b)
+{
+    std::vector<vanse::BatchMember> mem(b->count);
+    std::vector<unsigned> owner;
+    unsigned begin = 0;
+    for (int k = 0; k < b->count; ++k) {
+        const Solver &s = b->members[k]->s;
+        vanse::BatchMember &m = mem[k];
+        m.a = vanse::step_args(s, s.t);
+        m.a.block = (unsigned)b->block;
+        m.a.row = 0;
+        m.a.flags = b->nt ? 1 : 0;
+        m.nblocks = (unsigned)((s.geo.ncells + b->block - 1) / b->block);
+        m.a.nblocks = m.nblocks;
+        m.block_begin = begin;
+        owner.insert(owner.end(), m.nblocks, (unsigned)k);
+        begin += m.nblocks;
+    }
+    b->nblocks = begin;
+    (void)hipFree(b->d_members);
+    (void)hipFree(b->d_owner);
+    b->d_members = nullptr;
+    b->d_owner = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc((void **)&b->d_members, sizeof(vanse::BatchMember) * b->count)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->d_owner, sizeof(unsigned) * owner.size())) != hipSuccess)
+        return bfail(b, VANSE_ENOMEM, std::string("vanse_batch: hipMalloc: ") + hipGetErrorString(e));
+    if ((e = hipMemcpy(b->d_members, mem.data(), sizeof(vanse::BatchMember) * b->count,
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->d_owner, owner.data(), sizeof(unsigned) * owner.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return bfail(b, VANSE_EDEVICE, std::string("vanse_batch: upload: ") + hipGetErrorString(e));
+    if (b->gexec) {
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    return VANSE_OK;
+}
+
+// Stage m(t_s + j) for j < k and t0 = t_s of every member and upload them.
+int batch_upload(vanse_batch *b, int k)
+{
+    const int slot = b->cur;
+    b->cur ^= 1;
+    hipError_t e = hipEventSynchronize(b->tab_done[slot]);  // staging buffer free again
+    if (e != hipSuccess) return bfail(b, VANSE_EDEVICE, "vanse_batch_step: event sync failed");
+    double *m = reinterpret_cast<double *>(b->h_tab[slot]);
+    long long *t0 = reinterpret_cast<long long *>(m + (size_t)b->chunk_cap * b->count);
+    for (int s = 0; s < b->count; ++s) {
+        const Solver &sv = b->members[s]->s;
+        t0[s] = sv.t;
+        for (int j = 0; j < k; ++j) m[(size_t)j * b->count + s] = vanse::modulation(sv.t + j, sv.period);
+    }
+    if ((e = hipMemcpyAsync(b->d_tab, b->h_tab[slot], tab_bytes(b), hipMemcpyHostToDevice,
+                            b->stream)) != hipSuccess ||
+        (e = hipEventRecord(b->tab_done[slot], b->stream)) != hipSuccess)
+        return bfail(b, VANSE_EDEVICE, std::string("vanse_batch_step: ") + hipGetErrorString(e));
+    return VANSE_OK;
+}
+
+hipError_t batch_launch(vanse_batch *b, int j, hipStream_t st)
+{
+    const double *mtab = reinterpret_cast<const double *>(b->d_tab);
+    const long long *t0 =
+        reinterpret_cast<const long long *>(b->d_tab + sizeof(double) * (size_t)b->chunk_cap * b->count);
+    return vanse::launch_batch_step(b->lattice, b->mode, b->nt, b->nblocks, (unsigned)b->block,
+                                    b->d_members, b->d_owner, mtab, t0, j, b->count, st);
+}
+
+// Capture `chunk` batched steps (j = 0 .. chunk-1) into an executable graph.
+int batch_capture(vanse_batch *b)
+{
+    hipStream_t cs = nullptr;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int j = 0; j < b->chunk && e == hipSuccess; ++j) e = batch_launch(b, j, cs);
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        b->gexec = nullptr;
+        return bfail(b, VANSE_EDEVICE, std::string("vanse_batch: graph capture: ") + hipGetErrorString(e));
+    }
+    return VANSE_OK;
+}
+
+int batch_run(vanse_batch *b, int64_t n, bool allow_graph)
+{
+    for (auto *h : b->members)
+        if (h->s.unstable) return bfail(b, VANSE_EUNSTABLE, "vanse_batch_step: a member is unstable");
+    while (n > 0) {
+        const int k = (int)std::min<int64_t>(n, b->chunk_cap);
+        int rc = batch_upload(b, k);
+        if (rc != VANSE_OK) return rc;
+        hipError_t e = hipSuccess;
+        if (allow_graph && b->chunk > 0 && k == b->chunk) {
+            if (!b->gexec && (rc = batch_capture(b)) != VANSE_OK) return rc;
+            e = hipGraphLaunch(b->gexec, b->stream);
+        } else {
+            for (int j = 0; j < k && e == hipSuccess; ++j) e = batch_launch(b, j, b->stream);
+        }
+        if (e != hipSuccess)
+            return bfail(b, VANSE_EDEVICE, std::string("vanse_batch_step: ") + hipGetErrorString(e));
+        for (auto *h : b->members) h->s.t += k;
+        n -= k;
+    }
+    return VANSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vanse_batch_create(const vanse_t *solvers, int count, vanse_batch_t *out)
+{
+    if (!out) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: out is NULL");
+    *out = nullptr;
+    if (!solvers || count < 1) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: no solvers");
+    for (int k = 0; k < count; ++k) {
+        if (!solvers[k]) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: NULL handle");
+        const Solver &s = solvers[k]->s;
+        if (!s.initialized)
+            return bfail(nullptr, VANSE_ESTATE, "vanse_batch_create: member not initialised");
+        if (s.lattice != solvers[0]->s.lattice || s.mode != solvers[0]->s.mode)
+            return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: members differ in lattice or dtype");
+        for (int l = 0; l < k; ++l)
+            if (solvers[l] == solvers[k])
+                return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: duplicate member");
+    }
+    auto *b = new (std::nothrow) vanse_batch();
+    if (!b) return bfail(nullptr, VANSE_ENOMEM, "vanse_batch_create: host allocation failed");
+    b->members.assign(solvers, solvers + count);
+    b->count = count;
+    b->lattice = solvers[0]->s.lattice;
+    b->mode = solvers[0]->s.mode;
+    b->stream = solvers[0]->s.stream;
+    b->chunk_cap = 16;
+    hipError_t e = hipSuccess;
+    if ((e = hipMalloc((void **)&b->d_tab, tab_bytes(b))) == hipSuccess)
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            e = hipHostMalloc((void **)&b->h_tab[k], tab_bytes(b), hipHostMallocDefault);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->tab_done[k], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(b->tab_done[k], b->stream);
+        }
+    int rc = (e == hipSuccess) ? batch_layout(b) : VANSE_ENOMEM;
+    if (rc != VANSE_OK) {
+        std::string msg = b->err.empty() ? std::string("vanse_batch_create: ") + hipGetErrorString(e) : b->err;
+        batch_free(b);
+        delete b;
+        (void)hipGetLastError();
+        return bfail(nullptr, rc, msg);
+    }
+    *out = b;
+    return VANSE_OK;
+}
+
+int vanse_batch_destroy(vanse_batch_t b)
+{
+    if (!b) return VANSE_OK;
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    delete b;
+    return VANSE_OK;
+}
+
+int vanse_batch_set_stream(vanse_batch_t b, void *stream)
+{
+    if (!b) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_set_stream: NULL batch");
+    // order the staging events with the new stream
+    (void)hipStreamSynchronize(b->stream);
+    b->stream = static_cast<hipStream_t>(stream);
+    return VANSE_OK;
+}
+
+int vanse_batch_set_tuning(vanse_batch_t b, int block, int flags, int chunk)
+{
+    if (!b) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_set_tuning: NULL batch");
+    if (block != 64 && block != 128 && block != 256)
+        return bfail(b, VANSE_EINVAL, "vanse_batch_set_tuning: block must be 64, 128 or 256");
+    if (flags & ~VANSE_TUNE_NONTEMPORAL)
+        return bfail(b, VANSE_EINVAL, "vanse_batch_set_tuning: only VANSE_TUNE_NONTEMPORAL applies");
+    if (chunk < 0 || chunk > b->chunk_cap)
+        return bfail(b, VANSE_EINVAL, "vanse_batch_set_tuning: chunk must be in [0, 16]");
+    const bool relayout = (block != b->block);
+    b->block = block;
+    b->nt = (flags & VANSE_TUNE_NONTEMPORAL) != 0;
+    b->chunk = chunk;
+    if (b->gexec) {
+        (void)hipStreamSynchronize(b->stream);
+        (void)hipGraphExecDestroy(b->gexec);
+        b->gexec = nullptr;
+    }
+    if (relayout) {
+        (void)hipStreamSynchronize(b->stream);
+        return batch_layout(b);
+    }
+    return VANSE_OK;
+}
+
+int vanse_batch_step(vanse_batch_t b, int64_t n)
+{
+    if (!b) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_step: NULL batch");
+    if (n < 0) return bfail(b, VANSE_EINVAL, "vanse_batch_step: n must be >= 0");
+    return batch_run(b, n, true);
+}
+
+int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *flags,
+                         int64_t *steps_run)
+{
+    if (!b) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_autotune: NULL batch");
+    if (steps_per_trial < 1) return bfail(b, VANSE_EINVAL, "vanse_batch_autotune: steps_per_trial < 1");
+    int64_t cells = 0;
+    for (auto *h : b->members) cells += h->s.geo.ncells;
+    int cls = 0;
+    while ((int64_t(1) << (cls + 1)) <= cells) ++cls;
+    const auto key = std::make_tuple(b->lattice, b->mode, cls);
+    int best_block = 256, best_flags = 0;
+    int64_t run = 0;
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            best_block = it->second.first;
+            best_flags = it->second.second;
+            cached = true;
+        }
+    }
+    if (!cached) {
+        const int blocks[3] = {64, 128, 256};
+        float best = 1e30f;
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return bfail(b, VANSE_EDEVICE, "vanse_batch_autotune: event creation failed");
+        int rc = VANSE_OK;
+        for (int bi = 0; bi < 3 && rc == VANSE_OK; ++bi)
+            for (int fl = 0; fl <= 1 && rc == VANSE_OK; ++fl) {
+                if ((rc = vanse_batch_set_tuning(b, blocks[bi], fl, b->chunk)) != VANSE_OK) break;
+                (void)hipEventRecord(e0, b->stream);
+                if ((rc = batch_run(b, steps_per_trial, false)) != VANSE_OK) break;
+                (void)hipEventRecord(e1, b->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                run += steps_per_trial;
+                if (ms < best) {
+                    best = ms;
+                    best_block = blocks[bi];
+                    best_flags = fl;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != VANSE_OK) return rc;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {best_block, best_flags};
+    }
+    int rc = vanse_batch_set_tuning(b, best_block, best_flags, b->chunk);
+    if (rc != VANSE_OK) return rc;
+    if (block) *block = best_block;
+    if (flags) *flags = best_flags;
+    if (steps_run) *steps_run = run;
+    return VANSE_OK;
+}
+
+const char *vanse_batch_last_error(vanse_batch_t b)
+{
+    return b ? b->err.c_str() : g_batch_error.c_str();
 }
 
 }  // extern "C"

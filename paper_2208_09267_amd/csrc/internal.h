@@ -58,6 +58,13 @@ struct StepArgs {
     FastDiv fd_nx, fd_ny, fd_seg;
 };
 
+// One solve inside a batched launch (device-resident table).
+struct BatchMember {
+    StepArgs a;            // geometry, pointers and physics of the solve
+    unsigned block_begin;  // first block of the solve in the batched grid
+    unsigned nblocks;
+};
+
 struct Solver {
     int lattice = 0, mode = 0, d = 0, q = 0;
     Geometry geo{};
@@ -89,6 +96,10 @@ StepArgs step_args(const Solver &s, int64_t n);
 // Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_step(const Solver &s, const StepArgs &a, int parity);
 hipError_t launch_init(const Solver &s, const double *rho0, const double *u0);
+hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, unsigned block,
+                             const BatchMember *members, const unsigned *owner,
+                             const double *mtab, const long long *t0, int j, int count,
+                             hipStream_t st);
 hipError_t launch_moments(const Solver &s, int parity, double m, double *rho, double *p,
                           double *u);
 hipError_t launch_populations(const Solver &s, int parity, double *f);

@@ -277,67 +277,30 @@ __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R o
 }
 
 // ---------------------------------------------------------------------------
-// One fused time step (the hot path): Q population loads, the phi stencil,
-// the collision and Q stores for one cell per thread.
-//
-// ROW tiling (nx a multiple of the block size B): a block covers B
-// consecutive cells of one x-row, so the y/z neighbour rows are
-// wave-uniform; every access is a scalar row base plus a 32-bit lane offset
-// of x-1, x or x+1.  FLAT tiling (any size): the lattice is flattened and
-// divided with launch-invariant multipliers.
-// XCD remap (flags & 2): the hardware deals blocks round-robin over the 8
-// XCDs; the remap gives each XCD one contiguous range of blocks, so lines
-// shared by neighbouring blocks (shifted x accesses, phi neighbour rows) meet
-// in the same L2.
-template <class L, int MODE, int PARITY, bool ROW, bool NT>
-__global__ void __launch_bounds__(256) step_kernel(StepArgs a)
+// One fused time step of one cell (the hot path): Q population loads, the
+// phi stencil, the collision and Q stores.  (x, y, z) is the cell; its
+// periodic neighbour rows are the element offsets Yo (y-1, y, y+1) and Zo
+// (z-1, z, z+1).  Every access is a row base (wave-uniform under ROW
+// tiling) plus a 32-bit lane offset of x-1, x or x+1.
+template <class L, int MODE, int PARITY, bool NT>
+__device__ __forceinline__ void cell_step(const StepArgs &a, int x, int y, int z)
 {
     using St = Storage<MODE>;
     using T = typename St::T;
     using R = typename St::R;
-
-    unsigned b = blockIdx.x;
-    if (a.flags & 2) {
-        const unsigned q = a.nblocks >> 3, r = a.nblocks & 7, xcd = b & 7, idx = b >> 3;
-        b = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-    }
-    int x, y, z;
-    if constexpr (ROW) {
-        const unsigned row = fdiv(b, a.fd_seg);
-        const unsigned seg = b - row * a.nseg;
-        z = (int)fdiv(row, a.fd_ny);
-        y = (int)row - z * a.geo.ny;
-        x = (int)(seg * a.block + threadIdx.x);
-    } else {
-        const unsigned c = b * a.block + threadIdx.x;
-        if (c >= (unsigned)a.geo.ncells) return;
-        const unsigned yz = fdiv(c, a.fd_nx);
-        x = (int)(c - yz * a.geo.nx);
-        z = (int)fdiv(yz, a.fd_ny);
-        y = (int)yz - z * a.geo.ny;
-    }
     const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz;
     const int X[3] = {(x == 0 ? nx : x) - 1, x, (x + 1 == nx) ? 0 : x + 1};
     const int Yo[3] = {((y == 0 ? ny : y) - 1) * nx, y * nx, ((y + 1 == ny) ? 0 : y + 1) * nx};
     const int Zo[3] = {((z == 0 ? nz : z) - 1) * a.geo.nxy, z * a.geo.nxy,
                        ((z + 1 == nz) ? 0 : z + 1) * a.geo.nxy};
 
-    // element at offset (dx, dy, dz) of plane p: row base + lane offset
     auto load = [&](const T *plane, int dx, int dy, int dz) -> T {
-        if constexpr (ROW)
-            return ld<T, NT>(plane + (Zo[dz + 1] + Yo[dy + 1]),
-                             (unsigned)X[dx + 1] * (unsigned)sizeof(T));
-        else
-            return ld<T, NT>(plane, (unsigned)(Zo[dz + 1] + Yo[dy + 1] + X[dx + 1]) *
-                                        (unsigned)sizeof(T));
+        return ld<T, NT>(plane + (Zo[dz + 1] + Yo[dy + 1]),
+                         (unsigned)X[dx + 1] * (unsigned)sizeof(T));
     };
     auto store = [&](T *plane, int dx, int dy, int dz, T val) {
-        if constexpr (ROW)
-            st<T, NT>(plane + (Zo[dz + 1] + Yo[dy + 1]),
-                      (unsigned)X[dx + 1] * (unsigned)sizeof(T), val);
-        else
-            st<T, NT>(plane, (unsigned)(Zo[dz + 1] + Yo[dy + 1] + X[dx + 1]) *
-                                 (unsigned)sizeof(T), val);
+        st<T, NT>(plane + (Zo[dz + 1] + Yo[dy + 1]), (unsigned)X[dx + 1] * (unsigned)sizeof(T),
+                  val);
     };
 
     T *__restrict__ f = static_cast<T *>(a.f);
@@ -379,6 +342,66 @@ __global__ void __launch_bounds__(256) step_kernel(StepArgs a)
     });
 }
 
+// One time step of one solve.
+// ROW tiling (nx a multiple of the block size): a block covers `block`
+// consecutive cells of one x-row, so the y/z neighbour rows are
+// wave-uniform.  FLAT tiling (any size): the lattice is flattened and
+// divided with launch-invariant multipliers.
+// XCD remap (flags & 2): the hardware deals blocks round-robin over the 8
+// XCDs; the remap gives each XCD one contiguous range of blocks.
+template <class L, int MODE, int PARITY, bool ROW, bool NT>
+__global__ void __launch_bounds__(256) step_kernel(StepArgs a)
+{
+    unsigned b = blockIdx.x;
+    if (a.flags & 2) {
+        const unsigned q = a.nblocks >> 3, r = a.nblocks & 7, xcd = b & 7, idx = b >> 3;
+        b = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+    }
+    int x, y, z;
+    if constexpr (ROW) {
+        const unsigned row = fdiv(b, a.fd_seg);
+        const unsigned seg = b - row * a.nseg;
+        z = (int)fdiv(row, a.fd_ny);
+        y = (int)row - z * a.geo.ny;
+        x = (int)(seg * a.block + threadIdx.x);
+    } else {
+        const unsigned c = b * a.block + threadIdx.x;
+        if (c >= (unsigned)a.geo.ncells) return;
+        const unsigned yz = fdiv(c, a.fd_nx);
+        x = (int)(c - yz * a.geo.nx);
+        z = (int)fdiv(yz, a.fd_ny);
+        y = (int)yz - z * a.geo.ny;
+    }
+    cell_step<L, MODE, PARITY, NT>(a, x, y, z);
+}
+
+// One time step of many independent solves in one launch.  Block b belongs
+// to solve owner[b]; that solve's blocks are a contiguous range starting at
+// members[s].block_begin and tile its flattened lattice.  Each solve has its
+// own time level (parity t0[s] + j) and modulation mtab[j][s].  The per-cell
+// arithmetic is cell_step, so every solve evolves exactly as it would alone.
+template <class L, int MODE, bool NT>
+__global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__restrict__ members,
+                                                         const unsigned *__restrict__ owner,
+                                                         const double *__restrict__ mtab,
+                                                         const long long *__restrict__ t0,
+                                                         int j, int count)
+{
+    const unsigned s = owner[blockIdx.x];
+    StepArgs a = members[s].a;
+    a.m = mtab[(long long)j * count + s];
+    const unsigned c = (blockIdx.x - members[s].block_begin) * a.block + threadIdx.x;
+    if (c >= (unsigned)a.geo.ncells) return;
+    const unsigned yz = fdiv(c, a.fd_nx);
+    const int x = (int)(c - yz * a.geo.nx);
+    const int z = (int)fdiv(yz, a.fd_ny);
+    const int y = (int)yz - z * a.geo.ny;
+    if ((t0[s] + j) & 1)
+        cell_step<L, MODE, 1, NT>(a, x, y, z);
+    else
+        cell_step<L, MODE, 0, NT>(a, x, y, z);
+}
+
 // ---------------------------------------------------------------------------
 // FP64 view of one cell at time level n (parity = n & 1): populations in
 // natural order and the macroscopic quantities of eqs. density, velocity and
@@ -388,7 +411,6 @@ __device__ __forceinline__ void load_natural(const StepArgs &a, const Cell &k, i
                                              double (&fo)[L::Q])
 {
     using T = typename Storage<MODE>::T;
-    using R = typename Storage<MODE>::R;
     const T *__restrict__ f = static_cast<const T *>(a.f);
     const long long S = a.geo.stride;
     static_for<0, L::Q>([&](auto ic) {
@@ -644,6 +666,24 @@ hipError_t launch_step(const Solver &s, const StepArgs &a, int parity)
             nt ? go(T_{}, T_{}) : go(T_{}, F_{});
         else
             nt ? go(F_{}, T_{}) : go(F_{}, F_{});
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, unsigned block,
+                             const BatchMember *members, const unsigned *owner,
+                             const double *mtab, const long long *t0, int j, int count,
+                             hipStream_t st)
+{
+    return dispatch(lattice, mode, [&](auto lat, auto m) {
+        using L = decltype(lat);
+        constexpr int M = decltype(m)::value;
+        if (nt)
+            batch_step_kernel<L, M, true><<<nblocks, block, 0, st>>>(members, owner, mtab, t0, j,
+                                                                    count);
+        else
+            batch_step_kernel<L, M, false><<<nblocks, block, 0, st>>>(members, owner, mtab, t0,
+                                                                     j, count);
         return hipGetLastError();
     });
 }

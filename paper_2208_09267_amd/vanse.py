@@ -34,6 +34,9 @@ EXPORTS = [
     "vanse_set_force", "vanse_init", "vanse_step", "vanse_moments", "vanse_diagnostics",
     "vanse_populations", "vanse_time", "vanse_device_bytes", "vanse_last_error",
     "vanse_lattice_info", "vanse_copy_probe", "vanse_set_tuning",
+    "vanse_batch_create", "vanse_batch_destroy", "vanse_batch_set_stream",
+    "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
+    "vanse_batch_last_error",
 ]
 TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT = 1, 2, 4
 
@@ -79,6 +82,13 @@ def load_library(path: str = LIB_PATH):
             "vanse_lattice_info": (i, [i, P, P, P, P]),
             "vanse_copy_probe": (i, [P, P, i64, P]),
             "vanse_set_tuning": (i, [P, i, i]),
+            "vanse_batch_create": (i, [ctypes.POINTER(P), i, ctypes.POINTER(P)]),
+            "vanse_batch_destroy": (i, [P]),
+            "vanse_batch_set_stream": (i, [P, P]),
+            "vanse_batch_set_tuning": (i, [P, i, i, i]),
+            "vanse_batch_step": (i, [P, i64]),
+            "vanse_batch_autotune": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i), I64P]),
+            "vanse_batch_last_error": (ctypes.c_char_p, [P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -243,3 +253,52 @@ class Solver:
         b = ctypes.c_int64()
         self._check(self.lib.vanse_device_bytes(self.h, ctypes.byref(b)))
         return b.value
+
+
+class Batch:
+    """Many independent solves advanced together: one batched kernel launch
+    per time step (hipGraph-captured in chunks).  The solvers stay owned by
+    the caller and must outlive the batch."""
+
+    def __init__(self, solvers):
+        self.lib = load_library()
+        self.solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        rc = self.lib.vanse_batch_create(arr, len(self.solvers), ctypes.byref(h))
+        if rc:
+            raise VanseError(rc, self.lib.vanse_batch_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc:
+            raise VanseError(rc, self.lib.vanse_batch_last_error(self.h).decode())
+
+    def _bind_stream(self):
+        self._check(self.lib.vanse_batch_set_stream(self.h, _stream_handle()))
+
+    def set_tuning(self, block=256, flags=0, chunk=16):
+        self._check(self.lib.vanse_batch_set_tuning(self.h, int(block), int(flags), int(chunk)))
+
+    def step(self, n=1):
+        self._bind_stream()
+        self._check(self.lib.vanse_batch_step(self.h, int(n)))
+
+    def autotune(self, steps_per_trial=10):
+        """Returns (block, flags, steps_run); the trial steps are real steps."""
+        self._bind_stream()
+        b, f, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        self._check(self.lib.vanse_batch_autotune(self.h, int(steps_per_trial), ctypes.byref(b),
+                                                  ctypes.byref(f), ctypes.byref(n)))
+        return b.value, f.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vanse_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
