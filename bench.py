@@ -217,6 +217,36 @@ def precision_study():
     return out
 
 
+def serve_run(rate, duration, budget, cell_cap, seed=4):
+    """Poisson arrivals (rate per second for `duration` seconds) of D3Q19
+    requests (edge log-uniform in [32, 192], 500-5000 steps, tau in
+    [0.55, 1.0], seeded phi), FP32 shifted, served by the continuous-batching
+    loop under an HBM budget.  Latency = arrival -> moments in host memory."""
+    from paper_2208_09267_amd import serve
+    from paper_2208_09267_amd import workloads as W
+
+    arrivals = W.served_arrivals(rate=rate, duration=duration, seed=seed)
+    offered = sum(w.ncells * w.steps for _, w in arrivals) / duration
+    done = [0]
+
+    def log(res):
+        done[0] += 1
+        if done[0] % 50 == 0:
+            print("# served %d/%d (latency %.2f s)" % (done[0], len(arrivals), res.latency),
+                  file=sys.stderr, flush=True)
+
+    srv = serve.Server(budget_bytes=budget, cell_cap=cell_cap, log=log)
+    t0 = time.perf_counter()
+    results = srv.run(arrivals)
+    wall = time.perf_counter() - t0
+    out = serve.summarize(results, wall)
+    out.update({"rate_per_s": rate, "arrival_window_s": duration,
+                "offered_glups": offered / 1e9, "hbm_budget_gb": budget / 1e9,
+                "cell_cap": cell_cap, "batch_rebuilds": srv.stats["rebuilds"],
+                "chunks": srv.stats["chunks"]})
+    return out
+
+
 def cpu_baseline(w, pert, u0, seconds):
     """The CPU oracle (FP64, as it stands) on the same workload, timed for a
     bounded number of steps."""
@@ -251,6 +281,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--precision", action="store_true",
                     help="run the FP32/FP16 error study instead of the throughput bench")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the served request stream instead of the throughput bench")
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--duration", type=float, default=60.0)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--cell-cap", type=float, default=40e6)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -267,6 +303,11 @@ def main():
     if args.precision:
         torch.cuda.set_device(0)
         print(json.dumps({"precision": precision_study()}), flush=True)
+        return
+    if args.serve:
+        torch.cuda.set_device(0)
+        print(json.dumps({"served": serve_run(args.rate, args.duration, args.budget_gb * 1e9,
+                                              int(args.cell_cap))}), flush=True)
         return
 
     w = W.d3q19_256()

@@ -1,0 +1,238 @@
+"""Continuous-batching request loop for VANSE lattice Boltzmann solves on one
+GPU.
+
+Requests (a workload: size, tau, phi, steps) arrive over time.  The loop
+admits them first-come-first-served as device memory (an HBM budget) and a
+cap on the cells in flight allow, keeps every admitted solve's populations
+resident on the device, and advances ALL admitted solves together with the
+batched launch (one kernel per time step covering every solve; chunks of
+steps replay a captured graph).  A solve that reaches its step count is
+retired at the next chunk boundary: its moments are copied to the host and
+its memory is freed, which lets queued requests in.  Requests that arrive
+while others are on the GPU therefore overlap with them on the device.
+Because the per-cell arithmetic of the batched launch does not depend on
+the other members, every result is bitwise identical alone and in the mix.
+
+Latency = time the moments reach host memory - arrival time.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import vanse
+from . import workloads as W
+
+_Q = {"D2Q9": 9, "D3Q19": 19}
+_ELEM = {vanse.FP64: 8, vanse.FP32_SHIFTED: 4, vanse.FP16_SHIFTED: 2}
+_PERT = {vanse.FP64: 8, vanse.FP32_SHIFTED: 4, vanse.FP16_SHIFTED: 4}
+
+
+def state_bytes(lattice: str, dims, dtype: int) -> int:
+    """Device bytes one solve holds (the layout vanse_create allocates:
+    Q population planes and one phi plane of stride round_up(ncells, 128),
+    plus the reduction scratch)."""
+    n = int(np.prod(dims))
+    stride = (n + 127) // 128 * 128
+    return _Q[lattice] * stride * _ELEM[dtype] + stride * _PERT[dtype] + 8 * (7 * 1024 + 64)
+
+
+def admit_count(queue_bytes: Sequence[int], queue_cells: Sequence[int], used_bytes: int,
+                active_cells: int, n_active: int, budget_bytes: int, cell_cap: int,
+                max_active: int) -> int:
+    """How many requests at the head of the FCFS queue to admit now.
+
+    A request is admitted while its state fits in the remaining HBM budget,
+    the cells in flight stay within cell_cap (enough cells to saturate the
+    GPU; more only stretches every solve) and the member count stays within
+    max_active.  The head always goes first: no request overtakes another.
+    When nothing is active, the head is admitted even above cell_cap (but
+    never above the budget), so one large request cannot starve."""
+    k = 0
+    for b, c in zip(queue_bytes, queue_cells):
+        if used_bytes + b > budget_bytes or n_active + 1 > max_active:
+            break
+        if n_active > 0 and active_cells + c > cell_cap:
+            break
+        used_bytes += b
+        active_cells += c
+        n_active += 1
+        k += 1
+    return k
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    name: str
+    arrival: float
+    admit: float = float("nan")
+    finish: float = float("nan")
+    steps: int = 0
+    cells: int = 0
+    error: Optional[str] = None
+    rho: Optional[np.ndarray] = None
+    p: Optional[np.ndarray] = None
+    u: Optional[np.ndarray] = None
+
+    @property
+    def latency(self):
+        return self.finish - self.arrival
+
+
+@dataclasses.dataclass
+class _Active:
+    rid: int
+    work: W.Workload
+    solver: vanse.Solver
+    remaining: int
+    result: Result
+
+
+class Server:
+    """Continuous-batching loop.  budget_bytes: HBM the resident states may
+    use; cell_cap: cells in flight; chunk: steps between admissions (and per
+    captured graph)."""
+
+    def __init__(self, budget_bytes=200e9, cell_cap=40_000_000, max_active=4096, chunk=16,
+                 dtype=vanse.FP32_SHIFTED, keep_fields=False, autotune=True, log=None):
+        self.budget = int(budget_bytes)
+        self.cell_cap = int(cell_cap)
+        self.max_active = int(max_active)
+        self.chunk = int(chunk)
+        self.dtype = dtype
+        self.keep_fields = keep_fields
+        self.autotune = autotune
+        self.log = log
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stats = collections.Counter()
+        self.tuning = (256, 0)
+
+    def _start(self, rid, work: W.Workload, now) -> Tuple[Optional[_Active], Result]:
+        res = Result(rid, work.name, arrival=now, steps=work.steps, cells=work.ncells)
+        try:
+            s = vanse.Solver(work.lattice, work.dims, work.tau, self.dtype)
+            try:
+                s.set_porosity(work.eps_mean, W.fourier_eps_device(work.dims, work.seed, self.device),
+                               work.period, work.quad_axes)
+                s.set_force(work.force)
+                d = 2 if work.lattice == "D2Q9" else 3
+                s.init(None, W.taylor_green_device(work.dims, work.tgv_amp, self.device, d))
+            except Exception:
+                s.close()
+                raise
+        except (vanse.VanseError, ValueError) as e:
+            res.error = str(e)
+            return None, res
+        return _Active(rid, work, s, work.steps, res), res
+
+    def run(self, arrivals: Sequence[Tuple[float, W.Workload]], realtime=True) -> List[Result]:
+        """Serve `arrivals` (time in seconds from start, workload), in
+        arrival order.  realtime=False admits every request at time 0 (an
+        offline batch).  Returns one Result per request, in arrival order."""
+        arrivals = sorted(enumerate(arrivals), key=lambda r: r[1][0])
+        clock = time.perf_counter
+        t0 = clock()
+        queue = collections.deque()  # (rid, arrival, workload)
+        active: List[_Active] = []
+        results = {}
+        batch = None
+        dirty = False
+        i = 0
+        used = 0
+        while i < len(arrivals) or queue or active:
+            now = clock() - t0
+            while i < len(arrivals) and (not realtime or arrivals[i][1][0] <= now):
+                rid, (ta, work) = arrivals[i]
+                queue.append((rid, ta if realtime else 0.0, work))
+                i += 1
+            k = admit_count([state_bytes(w.lattice, w.dims, self.dtype) for _, _, w in queue],
+                            [w.ncells for _, _, w in queue], used,
+                            sum(a.work.ncells for a in active), len(active), self.budget,
+                            self.cell_cap, self.max_active)
+            if k == 0 and not active and queue:
+                # the head can never fit: fail it rather than wait forever
+                rid, ta, work = queue.popleft()
+                res = Result(rid, work.name, ta, steps=work.steps, cells=work.ncells,
+                             error="request needs %d bytes, over the HBM budget"
+                                   % state_bytes(work.lattice, work.dims, self.dtype))
+                res.finish = clock() - t0
+                results[rid] = res
+                continue
+            for _ in range(k):
+                rid, ta, work = queue.popleft()
+                act, res = self._start(rid, work, ta)
+                res.admit = clock() - t0
+                if act is None:
+                    res.finish = res.admit
+                    results[rid] = res
+                    self.stats["failed"] += 1
+                    continue
+                active.append(act)
+                used += state_bytes(work.lattice, work.dims, self.dtype)
+                dirty = True
+            if not active:
+                if i < len(arrivals) and realtime:
+                    time.sleep(max(0.0, arrivals[i][1][0] - (clock() - t0)))
+                continue
+            if dirty:
+                if batch is not None:
+                    batch.close()
+                batch = vanse.Batch([a.solver for a in active])
+                block, flags = self.tuning
+                if self.autotune:
+                    # trial steps are real steps: keep them within every member's count
+                    trial = min(a.remaining for a in active) // 6
+                    if trial >= 1:
+                        block, flags, ran = batch.autotune(min(trial, 4))
+                        self.tuning = (block, flags)
+                        for a in active:
+                            a.remaining -= ran
+                batch.set_tuning(block, flags, self.chunk)
+                dirty = False
+                self.stats["rebuilds"] += 1
+            step = min(self.chunk, min(a.remaining for a in active))
+            if step > 0:
+                batch.step(step)
+                for a in active:
+                    a.remaining -= step
+                self.stats["chunks"] += 1
+            torch.cuda.current_stream().synchronize()
+            done = [a for a in active if a.remaining <= 0]
+            if done:
+                batch.close()
+                batch = None
+                dirty = True
+                for a in done:
+                    rho, p, u = a.solver.moments()
+                    if self.keep_fields:
+                        a.result.rho, a.result.p, a.result.u = (rho.cpu().numpy(), p.cpu().numpy(),
+                                                                u.cpu().numpy())
+                    else:
+                        torch.cuda.current_stream().synchronize()
+                    a.result.finish = clock() - t0
+                    results[a.rid] = a.result
+                    used -= state_bytes(a.work.lattice, a.work.dims, self.dtype)
+                    a.solver.close()
+                    if self.log:
+                        self.log(a.result)
+                active = [a for a in active if a.remaining > 0]
+        if batch is not None:
+            batch.close()
+        return [results[r] for r in sorted(results)]
+
+
+def summarize(results: Sequence[Result], wall: float):
+    ok = [r for r in results if r.error is None]
+    lat = np.array([r.latency for r in ok]) if ok else np.array([float("nan")])
+    lups = sum(r.cells * r.steps for r in ok)
+    return {"requests": len(results), "completed": len(ok), "failed": len(results) - len(ok),
+            "latency_p50_s": float(np.percentile(lat, 50)),
+            "latency_p99_s": float(np.percentile(lat, 99)),
+            "latency_max_s": float(lat.max()), "makespan_s": wall,
+            "aggregate_mlups": lups / wall / 1e6 if wall > 0 else float("nan")}

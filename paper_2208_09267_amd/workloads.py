@@ -3,7 +3,8 @@
 This module holds input recipes only -- volume-fraction fields, initial
 velocity fields and workload definitions -- and none of the method's
 arithmetic.  Both the GPU path and the CPU oracle receive the arrays made
-here.  It depends on numpy only.
+here.  It depends on numpy (and on torch for the *_device variants, which
+evaluate the same recipes on the GPU for long request streams).
 
 All fields are cell arrays with x fastest, cell = (z*ny + y)*nx + x, node
 coordinates equal to the integer cell indices, periodic in every axis.
@@ -37,17 +38,59 @@ def fourier_eps(dims, seed, modes=8, kmax=4, amp=0.05, mean=0.75, lo=0.5, hi=1.0
     clipped to [lo, hi] and returned minus `mean`.  phi(x, t) = mean +
     m(t) * result stays in [lo, hi] for any |m| <= 1."""
     nx, ny, nz = (list(dims) + [1, 1])[:3]
-    rng = np.random.default_rng(seed)
     x, y, z = (np.arange(nx)[None, None, :], np.arange(ny)[None, :, None],
                np.arange(nz)[:, None, None])
     S = np.zeros((nz, ny, nx))
+    for k, theta in fourier_modes(seed, modes, kmax):
+        S += amp * np.cos(2 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz) + theta)
+    return (np.clip(mean + S, lo, hi) - mean).ravel()
+
+
+def fourier_modes(seed, modes=8, kmax=4):
+    """The (wave vector, phase) draws of fourier_eps for a seed."""
+    rng = np.random.default_rng(seed)
+    out = []
     for _ in range(modes):
         k = rng.integers(-kmax, kmax + 1, 3)
         while not k.any():
             k = rng.integers(-kmax, kmax + 1, 3)
-        theta = rng.uniform(0.0, 2.0 * np.pi)
-        S += amp * np.cos(2 * np.pi * (k[0] * x / nx + k[1] * y / ny + k[2] * z / nz) + theta)
-    return (np.clip(mean + S, lo, hi) - mean).ravel()
+        out.append((k, rng.uniform(0.0, 2.0 * np.pi)))
+    return out
+
+
+def fourier_eps_device(dims, seed, device, modes=8, kmax=4, amp=0.05, mean=0.75, lo=0.5,
+                       hi=1.0):
+    """fourier_eps evaluated on a torch device (same draws, FP64; the values
+    may differ from the numpy ones in the last bits).  For large request
+    streams, where generating inputs on the host would dominate."""
+    import torch
+
+    nx, ny, nz = (list(dims) + [1, 1])[:3]
+    x = torch.arange(nx, dtype=torch.float64, device=device).view(1, 1, nx)
+    y = torch.arange(ny, dtype=torch.float64, device=device).view(1, ny, 1)
+    z = torch.arange(nz, dtype=torch.float64, device=device).view(nz, 1, 1)
+    S = torch.zeros((nz, ny, nx), dtype=torch.float64, device=device)
+    for k, theta in fourier_modes(seed, modes, kmax):
+        S += amp * torch.cos(2 * np.pi * (float(k[0]) * x / nx + float(k[1]) * y / ny
+                                          + float(k[2]) * z / nz) + theta)
+    return (torch.clamp(mean + S, lo, hi) - mean).reshape(-1)
+
+
+def taylor_green_device(dims, amp, device, d=3):
+    """taylor_green on a torch device, SoA [d, ncells]."""
+    import torch
+
+    nx, ny, nz = (list(dims) + [1, 1])[:3]
+    x = torch.arange(nx, dtype=torch.float64, device=device).view(1, 1, nx)
+    y = torch.arange(ny, dtype=torch.float64, device=device).view(1, ny, 1)
+    z = torch.arange(nz, dtype=torch.float64, device=device).view(nz, 1, 1)
+    kx, ky, kz = 2 * np.pi / nx, 2 * np.pi / ny, 2 * np.pi / nz
+    ux = amp * torch.sin(kx * x) * torch.cos(ky * y) * torch.cos(kz * z)
+    uy = -amp * torch.cos(kx * x) * torch.sin(ky * y) * torch.cos(kz * z)
+    out = torch.zeros((d, nz * ny * nx), dtype=torch.float64, device=device)
+    out[0] = ux.reshape(-1)
+    out[1] = uy.reshape(-1)
+    return out
 
 
 def taylor_green(dims, amp):

@@ -1,0 +1,40 @@
+"""CPU tests of the serving loop's host logic: the admission policy (a pure
+function of the budget and the queue) and the state-size formula."""
+import pytest
+
+from paper_2208_09267_amd import serve, vanse
+
+GB = 1 << 30
+
+
+def test_fcfs_admits_while_budget_and_cells_allow():
+    qb, qc = [10 * GB, 20 * GB, 5 * GB], [100, 200, 50]
+    assert serve.admit_count(qb, qc, 0, 0, 0, 100 * GB, 10_000, 64) == 3
+    assert serve.admit_count(qb, qc, 75 * GB, 0, 0, 100 * GB, 10_000, 64) == 1
+    # the head blocks: the small third request does not overtake the second
+    assert serve.admit_count(qb, qc, 75 * GB, 0, 1, 100 * GB, 10_000, 64) == 1
+    assert serve.admit_count(qb, qc, 95 * GB, 0, 1, 100 * GB, 10_000, 64) == 0
+
+
+def test_cell_cap_and_member_cap():
+    qb, qc = [1, 1, 1, 1], [40, 40, 40, 40]
+    assert serve.admit_count(qb, qc, 0, 0, 0, 100, 100, 64) == 2
+    assert serve.admit_count(qb, qc, 0, 30, 1, 100, 100, 64) == 1
+    assert serve.admit_count(qb, qc, 0, 0, 0, 100, 1000, 3) == 3
+    assert serve.admit_count(qb, qc, 0, 0, 62, 100, 1000, 64) == 2
+
+
+def test_idle_gpu_admits_one_oversized_request_but_never_over_budget():
+    assert serve.admit_count([5], [10_000], 0, 0, 0, 10, 100, 64) == 1
+    assert serve.admit_count([5, 5], [10_000, 1], 0, 0, 0, 10, 100, 64) == 1
+    assert serve.admit_count([50], [1], 0, 0, 0, 10, 100, 64) == 0
+    assert serve.admit_count([], [], 0, 0, 0, 10, 100, 64) == 0
+
+
+@pytest.mark.parametrize("dtype,elem,pert", [(vanse.FP64, 8, 8), (vanse.FP32_SHIFTED, 4, 4),
+                                             (vanse.FP16_SHIFTED, 2, 4)])
+def test_state_bytes_formula(dtype, elem, pert):
+    n = 33 * 17 * 5
+    stride = (n + 127) // 128 * 128
+    want = 19 * stride * elem + stride * pert + 8 * (7 * 1024 + 64)
+    assert serve.state_bytes("D3Q19", (33, 17, 5), dtype) == want
