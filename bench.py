@@ -247,6 +247,31 @@ def serve_run(rate, duration, budget, cell_cap, seed=4):
     return out
 
 
+def copy_probe(nbytes=1 << 30, reps=10):
+    """Plain device-to-device copy through the library's copy kernel: the
+    achievable streaming bandwidth (context for the roofline fraction) and
+    the calibration kernel of the HBM traffic counters."""
+    import torch
+
+    from paper_2208_09267_amd import vanse
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    vanse.copy_probe(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        vanse.copy_probe(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert torch.equal(dst[:1024], src[:1024])
+    return {"bytes_copied": nbytes, "ms": round(ms, 4),
+            "gb_s": round(2 * nbytes / (ms / 1e3) / 1e9, 1),
+            "frac_hbm": round(2 * nbytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def cpu_baseline(w, pert, u0, seconds):
     """The CPU oracle (FP64, as it stands) on the same workload, timed for a
     bounded number of steps."""
@@ -279,6 +304,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--precision", action="store_true",
                     help="run the FP32/FP16 error study instead of the throughput bench")
     ap.add_argument("--serve", action="store_true",
@@ -355,6 +381,8 @@ def main():
                          "gb_s": round(x["gb_s"], 1), "frac_hbm": round(x["frac_hbm"], 4),
                          "bytes_per_lup": x["bytes_per_lup"]} for v, x in results.items()},
     }
+    if not args.no_copy_probe:
+        out["copy_probe"] = copy_probe()
     if not args.no_batched:
         out["batched"] = batched_run()
         print("# batched: %s" % json.dumps(out["batched"]), file=sys.stderr, flush=True)
