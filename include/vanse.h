@@ -128,15 +128,21 @@ int vanse_diagnostics(vanse_t h, double out[7]);
  * library's direction order (vanse_lattice_info).  Asynchronous. */
 int vanse_populations(vanse_t h, double *f);
 
-/* Launch shape of the step kernel.  block: threads per block, 64, 128 or
- * 256.  flags: bitwise OR of
- *   VANSE_TUNE_NONTEMPORAL  population loads/stores carry the nontemporal hint
+/* Launch shape of the step kernel.  block: threads per block, 64, 128, 256,
+ * 512 or 1024.  flags: bitwise OR of
+ *   VANSE_TUNE_NONTEMPORAL  population loads and stores carry the nontemporal hint
  *   VANSE_TUNE_XCD_REMAP    each XCD processes one contiguous range of blocks
  *   VANSE_TUNE_FLAT         flattened tiling even when nx is a multiple of block
+ *   VANSE_TUNE_NT_STORES    only the population stores carry the nontemporal hint
  * Without VANSE_TUNE_FLAT a block covers `block` consecutive cells of one
  * x-row when nx % block == 0.  Every setting computes bitwise-identical
  * results; only speed differs.  Errors: EINVAL. */
-enum { VANSE_TUNE_NONTEMPORAL = 1, VANSE_TUNE_XCD_REMAP = 2, VANSE_TUNE_FLAT = 4 };
+enum {
+    VANSE_TUNE_NONTEMPORAL = 1,
+    VANSE_TUNE_XCD_REMAP = 2,
+    VANSE_TUNE_FLAT = 4,
+    VANSE_TUNE_NT_STORES = 8
+};
 int vanse_set_tuning(vanse_t h, int block, int flags);
 
 /* ---------------------------------------------------------------------------
@@ -180,6 +186,26 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
 
 /* Last error message of b (NULL: of the last failed vanse_batch_create). */
 const char *vanse_batch_last_error(vanse_batch_t b);
+
+/* Tile of the step kernel: a block covers tile_x consecutive cells (a power
+ * of two in [64, 1024]) of each of tile_y consecutive x-rows of one z-plane;
+ * tile_x * tile_y <= 1024 threads.  Used when the tile divides nx and ny (and
+ * VANSE_TUNE_FLAT is not set), else the flattened launch with
+ * tile_x * tile_y threads per block.  vanse_set_tuning resets the tile to
+ * (block, 1).  Results are bitwise identical for every tile.
+ * Errors: EINVAL. */
+int vanse_set_tile(vanse_t h, int tile_x, int tile_y);
+
+/* Autotune the launch shape of vanse_step: each candidate (tiled 256-cell
+ * row segments with 1, 2 or 4 rows per block where they divide the
+ * lattice; flat launches of 256, 512 and 1024 threads) runs
+ * `steps_per_trial` REAL steps timed with HIP events, and the fastest is
+ * kept and cached for solves of the same lattice, dtype and size class.
+ * The solve advances (number of candidates) * steps_per_trial steps, or 0
+ * when the choice came from the cache (*steps_run tells).  Synchronises.
+ * Errors: EINVAL, ESTATE, EDEVICE. */
+int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int *flags,
+                   int64_t *steps_run);
 
 /* Current time level n (number of steps since vanse_init). */
 int vanse_time(vanse_t h, int64_t *t);

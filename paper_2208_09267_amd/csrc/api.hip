@@ -66,14 +66,20 @@ StepArgs step_args(const Solver &s, int64_t n)
     a.n2 = 2.0 * n_axes;
     a.qmask = s.qmask;
     a.flags = s.flags;
-    a.block = (unsigned)s.block;
-    a.row = (s.allow_row && s.geo.nx % s.block == 0) ? 1 : 0;
-    a.nseg = a.row ? (unsigned)(s.geo.nx / s.block) : 1u;
-    a.nblocks = a.row ? a.nseg * (unsigned)s.geo.ny * (unsigned)s.geo.nz
-                      : (unsigned)((s.geo.ncells + s.block - 1) / s.block);
+    a.block = (unsigned)(s.tile_x * s.tile_y);
+    a.row = (s.allow_row && s.geo.nx % s.tile_x == 0 && s.geo.ny % s.tile_y == 0) ? 1 : 0;
+    a.tx = (unsigned)s.tile_x;
+    a.txlog = 0;
+    while ((1u << a.txlog) < a.tx) ++a.txlog;
+    a.ty = (unsigned)s.tile_y;
+    a.nseg = a.row ? (unsigned)(s.geo.nx / s.tile_x) : 1u;
+    a.nyb = a.row ? (unsigned)(s.geo.ny / s.tile_y) : 1u;
+    a.nblocks = a.row ? a.nseg * a.nyb * (unsigned)s.geo.nz
+                      : (unsigned)((s.geo.ncells + a.block - 1) / a.block);
     a.fd_nx = make_fastdiv((unsigned)s.geo.nx);
     a.fd_ny = make_fastdiv((unsigned)s.geo.ny);
     a.fd_seg = make_fastdiv(a.nseg);
+    a.fd_nyb = make_fastdiv(a.nyb);
     return a;
 }
 
@@ -332,13 +338,107 @@ int vanse_set_tuning(vanse_t h, int block, int flags)
 {
     if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_set_tuning: NULL handle");
     Solver &s = h->s;
-    if (block != 64 && block != 128 && block != 256)
-        return fail(&s, VANSE_EINVAL, "vanse_set_tuning: block must be 64, 128 or 256");
-    if (flags & ~(VANSE_TUNE_NONTEMPORAL | VANSE_TUNE_XCD_REMAP | VANSE_TUNE_FLAT))
+    if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
+        return fail(&s, VANSE_EINVAL, "vanse_set_tuning: block must be 64, 128, 256, 512 or 1024");
+    if (flags & ~(VANSE_TUNE_NONTEMPORAL | VANSE_TUNE_XCD_REMAP | VANSE_TUNE_FLAT |
+                  VANSE_TUNE_NT_STORES))
         return fail(&s, VANSE_EINVAL, "vanse_set_tuning: unknown flag");
-    s.block = block;
-    s.flags = flags & (VANSE_TUNE_NONTEMPORAL | VANSE_TUNE_XCD_REMAP);
+    s.tile_x = block;
+    s.tile_y = 1;
+    s.flags = flags & (VANSE_TUNE_NONTEMPORAL | VANSE_TUNE_XCD_REMAP | VANSE_TUNE_NT_STORES);
     s.allow_row = (flags & VANSE_TUNE_FLAT) == 0;
+    return VANSE_OK;
+}
+
+int vanse_set_tile(vanse_t h, int tile_x, int tile_y)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_set_tile: NULL handle");
+    Solver &s = h->s;
+    if (tile_x < 64 || tile_x > 1024 || (tile_x & (tile_x - 1)))
+        return fail(&s, VANSE_EINVAL, "vanse_set_tile: tile_x must be a power of two in [64, 1024]");
+    if (tile_y < 1 || tile_x * tile_y > 1024)
+        return fail(&s, VANSE_EINVAL, "vanse_set_tile: tile_x * tile_y must be <= 1024");
+    s.tile_x = tile_x;
+    s.tile_y = tile_y;
+    return VANSE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+std::mutex g_solo_tune_mu;
+// (lattice, mode, log2 cells, nx % 256, ny % 4) -> (tile_x, tile_y, flat)
+std::map<std::tuple<int, int, int, int, int>, std::tuple<int, int, int>> g_solo_tune_cache;
+}  // namespace
+
+extern "C" {
+
+int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int *flags,
+                   int64_t *steps_run)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_autotune: NULL handle");
+    Solver &s = h->s;
+    if (steps_per_trial < 1) return fail(&s, VANSE_EINVAL, "vanse_autotune: steps_per_trial < 1");
+    if (!s.initialized) return fail(&s, VANSE_ESTATE, "vanse_autotune: call vanse_init first");
+    int cls = 0;
+    while ((int64_t(1) << (cls + 1)) <= (int64_t)s.geo.ncells) ++cls;
+    const auto key = std::make_tuple(s.lattice, s.mode, cls, s.geo.nx % 256, s.geo.ny % 4);
+    int bx = 256, by = 1, flat = 0;
+    int64_t run = 0;
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_solo_tune_mu);
+        auto it = g_solo_tune_cache.find(key);
+        if (it != g_solo_tune_cache.end()) {
+            std::tie(bx, by, flat) = it->second;
+            cached = true;
+        }
+    }
+    const int keep_flags = s.flags & ~VANSE_TUNE_FLAT;
+    if (!cached) {
+        // candidates: tiled x-row segments of 256 cells with 1, 2, 4 rows, and the
+        // flattened launch with 256, 512, 1024 threads
+        const int cand[6][3] = {{256, 1, 0}, {256, 2, 0}, {256, 4, 0},
+                                {256, 1, 1}, {512, 1, 1}, {1024, 1, 1}};
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return fail(&s, VANSE_EDEVICE, "vanse_autotune: event creation failed");
+        float best = 1e30f;
+        int rc = VANSE_OK;
+        for (int c = 0; c < 6 && rc == VANSE_OK; ++c) {
+            const bool tiled_ok = s.geo.nx % cand[c][0] == 0 && s.geo.ny % cand[c][1] == 0;
+            if (!cand[c][2] && !tiled_ok) continue;  // would fall back to a flat launch
+            s.tile_x = cand[c][0];
+            s.tile_y = cand[c][1];
+            s.allow_row = !cand[c][2];
+            (void)hipEventRecord(e0, s.stream);
+            rc = vanse_step(h, steps_per_trial);
+            (void)hipEventRecord(e1, s.stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            run += steps_per_trial;
+            if (rc == VANSE_OK && ms < best) {
+                best = ms;
+                bx = cand[c][0];
+                by = cand[c][1];
+                flat = cand[c][2];
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != VANSE_OK) return rc;
+        std::lock_guard<std::mutex> lk(g_solo_tune_mu);
+        g_solo_tune_cache[key] = std::make_tuple(bx, by, flat);
+    }
+    s.tile_x = bx;
+    s.tile_y = by;
+    s.allow_row = !flat;
+    s.flags = keep_flags;
+    if (tile_x) *tile_x = bx;
+    if (tile_y) *tile_y = by;
+    if (flags) *flags = keep_flags | (flat ? VANSE_TUNE_FLAT : 0);
+    if (steps_run) *steps_run = run;
     return VANSE_OK;
 }
 

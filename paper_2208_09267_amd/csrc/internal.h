@@ -50,12 +50,15 @@ struct StepArgs {
     double n2;           // 2 * (number of quadrature axes)
     int qmask;           // quadrature axes bitmask
     // launch shape
-    int row;             // 1: ROW tiling (nx % block == 0), 0: FLAT
-    int flags;           // 1: nontemporal population traffic, 2: XCD remap
+    int row;             // 1: tiled (tile divides the lattice), 0: FLAT
+    int flags;           // 1: nontemporal loads+stores, 2: XCD remap, 8: nontemporal stores
     unsigned block;      // threads per block
     unsigned nblocks;    // grid size
-    unsigned nseg;       // ROW: blocks per x-row
-    FastDiv fd_nx, fd_ny, fd_seg;
+    unsigned tx, txlog;  // tiled: cells of one x-row segment per block (2^txlog, >= 64)
+    unsigned ty;         // tiled: rows per block
+    unsigned nseg;       // tiled: segments per x-row (nx / tx)
+    unsigned nyb;        // tiled: row blocks per z-plane (ny / ty)
+    FastDiv fd_nx, fd_ny, fd_seg, fd_nyb;
 };
 
 // One solve inside a batched launch (device-resident table).
@@ -74,9 +77,10 @@ struct Solver {
     double F[3] = {0.0, 0.0, 0.0};
     bool porosity_set = false, initialized = false, unstable = false;
     int64_t t = 0;
-    int block = 256;             // threads per block of the step kernel
+    int tile_x = 256;            // step kernel tile: x-row segment per block
+    int tile_y = 1;              //   and rows per block
     int flags = 0;               // step-kernel variant flags (StepArgs::flags)
-    bool allow_row = true;       // use ROW tiling when nx allows it
+    bool allow_row = true;       // use the tiled launch when the tile divides the lattice
     void *f = nullptr;           // populations
     size_t f_bytes = 0;
     void *pert = nullptr;        // phi perturbation (double or float)

@@ -282,7 +282,8 @@ __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R o
 // periodic neighbour rows are the element offsets Yo (y-1, y, y+1) and Zo
 // (z-1, z, z+1).  Every access is a row base (wave-uniform under ROW
 // tiling) plus a 32-bit lane offset of x-1, x or x+1.
-template <class L, int MODE, int PARITY, bool NT>
+// NT: 0 plain accesses, 1 nontemporal loads and stores, 2 nontemporal stores.
+template <class L, int MODE, int PARITY, int NT>
 __device__ __forceinline__ void cell_step(const StepArgs &a, int x, int y, int z)
 {
     using St = Storage<MODE>;
@@ -295,11 +296,11 @@ __device__ __forceinline__ void cell_step(const StepArgs &a, int x, int y, int z
                        ((z + 1 == nz) ? 0 : z + 1) * a.geo.nxy};
 
     auto load = [&](const T *plane, int dx, int dy, int dz) -> T {
-        return ld<T, NT>(plane + (Zo[dz + 1] + Yo[dy + 1]),
+        return ld<T, NT == 1>(plane + (Zo[dz + 1] + Yo[dy + 1]),
                          (unsigned)X[dx + 1] * (unsigned)sizeof(T));
     };
     auto store = [&](T *plane, int dx, int dy, int dz, T val) {
-        st<T, NT>(plane + (Zo[dz + 1] + Yo[dy + 1]), (unsigned)X[dx + 1] * (unsigned)sizeof(T),
+        st<T, NT != 0>(plane + (Zo[dz + 1] + Yo[dy + 1]), (unsigned)X[dx + 1] * (unsigned)sizeof(T),
                   val);
     };
 
@@ -343,36 +344,41 @@ __device__ __forceinline__ void cell_step(const StepArgs &a, int x, int y, int z
 }
 
 // One time step of one solve.
-// ROW tiling (nx a multiple of the block size): a block covers `block`
-// consecutive cells of one x-row, so the y/z neighbour rows are
-// wave-uniform.  FLAT tiling (any size): the lattice is flattened and
-// divided with launch-invariant multipliers.
+// Tiled launch (the tile divides the lattice): a block covers tx consecutive
+// cells of each of ty consecutive x-rows of one z-plane; every wave lies
+// inside one row, so the y/z neighbour rows are wave-uniform (scalar
+// registers), and the phi rows a block re-reads (y +- 1 inside the block)
+// come from the CU's caches.  FLAT launch (any size): the lattice is flattened
+// and divided with launch-invariant multipliers.
 // XCD remap (flags & 2): the hardware deals blocks round-robin over the 8
 // XCDs; the remap gives each XCD one contiguous range of blocks.
-template <class L, int MODE, int PARITY, bool ROW, bool NT>
-__global__ void __launch_bounds__(256) step_kernel(StepArgs a)
+template <class L, int MODE, int PARITY, bool ROW, int NT>
+__global__ void __launch_bounds__(1024) step_kernel(StepArgs a)
 {
     unsigned b = blockIdx.x;
     if (a.flags & 2) {
         const unsigned q = a.nblocks >> 3, r = a.nblocks & 7, xcd = b & 7, idx = b >> 3;
         b = (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
     }
-    int x, y, z;
     if constexpr (ROW) {
-        const unsigned row = fdiv(b, a.fd_seg);
-        const unsigned seg = b - row * a.nseg;
-        z = (int)fdiv(row, a.fd_ny);
-        y = (int)row - z * a.geo.ny;
-        x = (int)(seg * a.block + threadIdx.x);
+        const unsigned rb = fdiv(b, a.fd_seg);
+        const unsigned seg = b - rb * a.nseg;
+        const unsigned zb = fdiv(rb, a.fd_nyb);
+        const unsigned yb = rb - zb * a.nyb;
+        // tx is a multiple of 64: all lanes of a wave share the row
+        const unsigned ty = __builtin_amdgcn_readfirstlane(threadIdx.x >> a.txlog);
+        const int x = (int)(seg * a.tx + (threadIdx.x & (a.tx - 1)));
+        const int y = (int)(yb * a.ty + ty);
+        cell_step<L, MODE, PARITY, NT>(a, x, y, (int)zb);
     } else {
         const unsigned c = b * a.block + threadIdx.x;
         if (c >= (unsigned)a.geo.ncells) return;
         const unsigned yz = fdiv(c, a.fd_nx);
-        x = (int)(c - yz * a.geo.nx);
-        z = (int)fdiv(yz, a.fd_ny);
-        y = (int)yz - z * a.geo.ny;
+        const int x = (int)(c - yz * a.geo.nx);
+        const int z = (int)fdiv(yz, a.fd_ny);
+        const int y = (int)yz - z * a.geo.ny;
+        cell_step<L, MODE, PARITY, NT>(a, x, y, z);
     }
-    cell_step<L, MODE, PARITY, NT>(a, x, y, z);
 }
 
 // One time step of many independent solves in one launch.  Block b belongs
@@ -397,9 +403,9 @@ __global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__re
     const int z = (int)fdiv(yz, a.fd_ny);
     const int y = (int)yz - z * a.geo.ny;
     if ((t0[s] + j) & 1)
-        cell_step<L, MODE, 1, NT>(a, x, y, z);
+        cell_step<L, MODE, 1, NT ? 1 : 0>(a, x, y, z);
     else
-        cell_step<L, MODE, 0, NT>(a, x, y, z);
+        cell_step<L, MODE, 0, NT ? 1 : 0>(a, x, y, z);
 }
 
 // ---------------------------------------------------------------------------
@@ -649,24 +655,30 @@ static hipError_t dispatch(int lattice, int mode, Fn &&fn)
 
 hipError_t launch_step(const Solver &s, const StepArgs &a, int parity)
 {
-    const bool nt = (a.flags & 1) != 0;
+    const int nt = (a.flags & 1) ? 1 : ((a.flags & 8) ? 2 : 0);
     return dispatch(s.lattice, s.mode, [&](auto lat, auto mode) {
         using L = decltype(lat);
         constexpr int M = decltype(mode)::value;
         auto go = [&](auto row_c, auto nt_c) {
             constexpr bool ROW = decltype(row_c)::value;
-            constexpr bool NT = decltype(nt_c)::value;
+            constexpr int NT = decltype(nt_c)::value;
             if (parity == 0)
                 step_kernel<L, M, 0, ROW, NT><<<a.nblocks, a.block, 0, s.stream>>>(a);
             else
                 step_kernel<L, M, 1, ROW, NT><<<a.nblocks, a.block, 0, s.stream>>>(a);
         };
-        using T_ = std::true_type;
-        using F_ = std::false_type;
+        auto by_nt = [&](auto row_c) {
+            if (nt == 1)
+                go(row_c, std::integral_constant<int, 1>{});
+            else if (nt == 2)
+                go(row_c, std::integral_constant<int, 2>{});
+            else
+                go(row_c, std::integral_constant<int, 0>{});
+        };
         if (a.row)
-            nt ? go(T_{}, T_{}) : go(T_{}, F_{});
+            by_nt(std::true_type{});
         else
-            nt ? go(F_{}, T_{}) : go(F_{}, F_{});
+            by_nt(std::false_type{});
         return hipGetLastError();
     });
 }

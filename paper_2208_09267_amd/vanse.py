@@ -33,12 +33,13 @@ EXPORTS = [
     "vanse_create", "vanse_destroy", "vanse_set_stream", "vanse_set_porosity",
     "vanse_set_force", "vanse_init", "vanse_step", "vanse_moments", "vanse_diagnostics",
     "vanse_populations", "vanse_time", "vanse_device_bytes", "vanse_last_error",
-    "vanse_lattice_info", "vanse_copy_probe", "vanse_set_tuning",
+    "vanse_lattice_info", "vanse_copy_probe", "vanse_set_tuning", "vanse_set_tile",
+    "vanse_autotune",
     "vanse_batch_create", "vanse_batch_destroy", "vanse_batch_set_stream",
     "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
     "vanse_batch_last_error",
 ]
-TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT = 1, 2, 4
+TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT, TUNE_NT_STORES = 1, 2, 4, 8
 
 
 class VanseError(RuntimeError):
@@ -82,6 +83,9 @@ def load_library(path: str = LIB_PATH):
             "vanse_lattice_info": (i, [i, P, P, P, P]),
             "vanse_copy_probe": (i, [P, P, i64, P]),
             "vanse_set_tuning": (i, [P, i, i]),
+            "vanse_set_tile": (i, [P, i, i]),
+            "vanse_autotune": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i),
+                                   ctypes.POINTER(i), I64P]),
             "vanse_batch_create": (i, [ctypes.POINTER(P), i, ctypes.POINTER(P)]),
             "vanse_batch_destroy": (i, [P]),
             "vanse_batch_set_stream": (i, [P, P]),
@@ -197,9 +201,22 @@ class Solver:
                                                 float(period), int(quad_axes)))
 
     def set_tuning(self, block=256, flags=0):
-        """Threads per block (64/128/256) and TUNE_* flags of the step kernel;
+        """Threads per block (64 .. 1024) and TUNE_* flags of the step kernel;
         results are bitwise identical for every setting."""
         self._check(self.lib.vanse_set_tuning(self.h, int(block), int(flags)))
+
+    def set_tile(self, tile_x=256, tile_y=1):
+        """Tile of the step kernel (see vanse_set_tile); bitwise-neutral."""
+        self._check(self.lib.vanse_set_tile(self.h, int(tile_x), int(tile_y)))
+
+    def autotune(self, steps_per_trial=4):
+        """Pick the fastest launch shape on real steps (see vanse_autotune).
+        Returns (tile_x, tile_y, flags, steps_run)."""
+        self._bind_stream()
+        bx, by, fl, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        self._check(self.lib.vanse_autotune(self.h, int(steps_per_trial), ctypes.byref(bx),
+                                            ctypes.byref(by), ctypes.byref(fl), ctypes.byref(n)))
+        return bx.value, by.value, fl.value, n.value
 
     def set_force(self, F):
         F = list(F) + [0.0] * (3 - len(F))

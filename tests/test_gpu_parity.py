@@ -172,12 +172,12 @@ def test_device_side_validation_and_state_errors():
 
 @pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
 def test_every_launch_shape_is_bitwise_identical(dtype):
-    dims = (128, 6, 5)  # nx a multiple of every block size: ROW and FLAT both reachable
+    dims = (128, 6, 5)  # ROW tiling for blocks up to 128, FLAT above and with VANSE_TUNE_FLAT
     pert = W.fourier_eps(dims, seed=9)
     u0 = torch.from_numpy(np.ascontiguousarray(W.taylor_green(dims, 0.02))).cuda()
     ref = None
-    for block in (64, 128, 256):
-        for flags in (0, 1, 2, 3, 4, 6):
+    for block in (64, 128, 256, 512, 1024):
+        for flags in (0, 1, 2, 3, 4, 6, 8, 12):
             s = vanse.Solver("D3Q19", dims, 0.57, dtype)
             s.set_tuning(block, flags)
             s.set_porosity(0.75, torch.from_numpy(pert).cuda(), 40.0)
@@ -189,3 +189,44 @@ def test_every_launch_shape_is_bitwise_identical(dtype):
             if ref is None:
                 ref = f
             assert np.array_equal(f, ref), (block, flags)
+
+
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+def test_every_tile_is_bitwise_identical(dtype):
+    dims = (128, 8, 6)
+    pert = W.fourier_eps(dims, seed=10)
+    u0 = torch.from_numpy(np.ascontiguousarray(W.taylor_green(dims, 0.02))).cuda()
+    ref = None
+    for tile in [(64, 1), (128, 8), (64, 4), (128, 2), (64, 8), (256, 2), (64, 16), (128, 4),
+                 (256, 4), (512, 2)]:
+        s = vanse.Solver("D3Q19", dims, 0.61, dtype)
+        s.set_tile(*tile)
+        s.set_porosity(0.75, torch.from_numpy(pert).cuda(), 30.0)
+        s.set_force((-1e-6, 2e-6, 0.0))
+        s.init(None, u0)
+        s.step(11)
+        f = s.populations().cpu().numpy()
+        s.close()
+        if ref is None:
+            ref = f
+        assert np.array_equal(f, ref), tile
+
+
+def test_autotune_is_bitwise_neutral_and_counts_its_steps():
+    dims = (256, 8, 6)
+    pert = torch.from_numpy(W.fourier_eps(dims, seed=12)).cuda()
+    u0 = torch.from_numpy(np.ascontiguousarray(W.taylor_green(dims, 0.02))).cuda()
+    a = vanse.Solver("D3Q19", dims, 0.6, vanse.FP32_SHIFTED)
+    b = vanse.Solver("D3Q19", dims, 0.6, vanse.FP32_SHIFTED)
+    for s in (a, b):
+        s.set_porosity(0.75, pert, 50.0)
+        s.init(None, u0)
+    tx, ty, flags, ran = a.autotune(2)
+    assert ran == 12 and a.time == 12  # 3 tiled + 3 flat candidates
+    a.step(7)
+    b.step(19)
+    assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
+    # same size class again: cached, no steps
+    assert b.autotune(2) == (tx, ty, flags, 0)
+    a.close()
+    b.close()
