@@ -105,6 +105,45 @@ def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
             "mass": mass, "launch": launch}
 
 
+def d3q27_run(steps=200, warmup=30):
+    """The paper's own 3-D lattice (D3Q27, Table 2) on the same 256^3
+    workload: FP64 and FP32 shifted."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_2208_09267_amd import vanse
+    from paper_2208_09267_amd import workloads as W
+
+    w = dataclasses.replace(W.d3q19_256(), lattice="D3Q27")
+    dev = torch.device("cuda", 0)
+    pert = torch.from_numpy(w.eps_pert()).to(dev)
+    u0 = torch.from_numpy(np.ascontiguousarray(w.u0())).to(dev)
+    out = {}
+    for name, dt, bpl in (("fp64", vanse.FP64, 27 * 8 * 2 + 8),
+                          ("fp32_shifted", vanse.FP32_SHIFTED, 27 * 4 * 2 + 4)):
+        s = vanse.Solver("D3Q27", w.dims, w.tau, dt)
+        s.set_porosity(w.eps_mean, pert, w.period)
+        s.init(None, u0)
+        tx, ty, flags, ran = s.autotune(4)
+        s.step(max(0, warmup - ran))
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        s.close()
+        gbs = bpl * w.ncells / (ms / 1e3) / 1e9
+        out[name] = {"mlups": round(w.ncells / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5),
+                     "bytes_per_lup": bpl, "gb_s": round(gbs, 1),
+                     "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
+                     "launch": {"tile_x": tx, "tile_y": ty, "flat": bool(flags & 4)}}
+    return out
+
+
 def batched_run(steps=500, trial=5):
     """64 independent D3Q19 solves (edges 32/48/64/96, tau in [0.55, 1],
     own seeded phi each), FP32 shifted, advanced together by the batched
@@ -321,6 +360,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--no-d3q27", action="store_true")
     ap.add_argument("--fixed-launch", action="store_true",
                     help="use the recorded launch shapes instead of autotuning")
     ap.add_argument("--precision", action="store_true",
@@ -405,6 +445,9 @@ def main():
     }
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe()
+    if not args.no_d3q27:
+        out["d3q27_256"] = d3q27_run()
+        print("# d3q27: %s" % json.dumps(out["d3q27_256"]), file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = batched_run()
         print("# batched: %s" % json.dumps(out["batched"]), file=sys.stderr, flush=True)

@@ -45,9 +45,14 @@ extern "C" {
 
 typedef struct vanse_solver *vanse_t;
 
-/* Lattices: D2Q9 (Table 1) and D3Q19 (the rest, face and edge groups of
- * Table 2 with weights 1/3, 1/18, 1/36). */
-enum { VANSE_D2Q9 = 0, VANSE_D3Q19 = 1 };
+/* Lattices: D2Q9 (Table 1), D3Q19 (the rest, face and edge groups of
+ * Table 2 with weights 1/3, 1/18, 1/36) and D3Q27 (Table 2). */
+enum { VANSE_D2Q9 = 0, VANSE_D3Q19 = 1, VANSE_D3Q27 = 2 };
+
+/* quad_axes value that switches the cell-integral correction off: I = phi,
+ * i.e. rho = sum f / phi (the density definition the paper corrects); for
+ * ablation studies only. */
+enum { VANSE_QUAD_NONE = 8 };
 
 /* Population storage.  FP64: f_i in binary64, FP64 arithmetic.
  * FP32_SHIFTED: g_i = f_i - w_i in binary32, FP32 arithmetic in deviation
@@ -65,7 +70,7 @@ enum {
 };
 
 /* Create a solver on the current HIP device.
- *   lattice  VANSE_D2Q9 or VANSE_D3Q19
+ *   lattice  VANSE_D2Q9, VANSE_D3Q19 or VANSE_D3Q27
  *   dims     {nx, ny, nz}, each >= 1; nz must be 1 for D2Q9;
  *            nx*ny*nz < 2^31
  *   tau      BGK relaxation time, finite and > 1/2 (eq. lbe; the recovered
@@ -91,7 +96,8 @@ int vanse_set_stream(vanse_t h, void *stream);
  *              free it on return
  *   quad_axes  bitmask of the axes the cell-integral quadrature runs over
  *              (1 = x, 2 = y, 4 = z; the D1Q3 / D2Q5 / D3Q7 choice of the
- *              paper, diagonals excluded); 0 selects all d axes
+ *              paper, diagonals excluded); 0 selects all d axes;
+ *              VANSE_QUAD_NONE drops the correction (I = phi)
  * Validates on the device that phi stays in (0, 1] for every reachable m and
  * that eps_pert is finite; synchronises.  Errors: EINVAL, EDEVICE. */
 int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, double period,
@@ -101,6 +107,13 @@ int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, doubl
  * units), added to the pressure-correction force in sum_k F_k.  Components
  * beyond the lattice dimension must be 0.  Errors: EINVAL. */
 int vanse_set_force(vanse_t h, const double F[3]);
+
+/* Per-cell external force density (phase-interaction or manufactured-
+ * solution forces; sum_k F_k of the Guo forcing term), added to F_ext and to
+ * the pressure-correction force.  F: device FP64 SoA [d][ncells], copied
+ * (to FP32 in the reduced modes; the first call allocates d planes);
+ * NULL switches the field off.  Asynchronous.  Errors: ENOMEM, EDEVICE. */
+int vanse_set_force_field(vanse_t h, const double *F);
 
 /* Initial populations (eq. equilibrium): f_i = f_i^eq of M0 = rho0 phi(x, 0)
  * and u0, with no non-equilibrium part.  rho0: device FP64 [ncells] or NULL

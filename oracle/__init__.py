@@ -31,6 +31,7 @@ _lock = threading.Lock()
 _lib = None
 
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
+QUAD_NONE = 8  # quad_axes value: no cell-integral correction (I = phi), ablation only
 _Q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}
 _D = {D2Q9: 2, D3Q19: 3, D3Q27: 3}
 
@@ -77,6 +78,7 @@ def _load():
             "oracle_mms_force_fd": (i, [i, P, d, d, d, P]),
             "oracle_mms_force_exact": (i, [i, P, d, d, P]),
             "oracle_mms_run": (i64, [i, i, i, d, d, i, i, P, P]),
+            "oracle_mms_run_q": (i64, [i, i, i, d, d, i, i, i, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -271,18 +273,21 @@ def mms_force_exact(example, X, t, nu=0.1):
     return F
 
 
-def mms_run(example, N, tau, t_end, lat=None, n_samples=1, nthreads=0):
+def mms_run(example, N, tau, t_end, lat=None, n_samples=1, nthreads=0, quad_axes=None):
     """Run one manufactured-solution example at resolution N.  Returns
     (errors[n_samples, 6], times[n_samples], nsteps); the error columns are
-    u L1, u L2, u Linf, p L1, p L2, p Linf in physical units."""
+    u L1, u L2, u Linf, p L1, p L2, p Linf in physical units.  quad_axes
+    overrides the example's quadrature (QUAD_NONE: the ablation)."""
     lib = _load()
     d, _, _ = mms_info(example)
     if lat is None:
         lat = D2Q9 if d == 2 else D3Q19
     errs = np.zeros((n_samples, 6))
     times = np.zeros(n_samples)
-    n = lib.oracle_mms_run(int(example), int(lat), int(N), float(tau), float(t_end),
-                           int(n_samples), int(nthreads), _ptr(errs), _ptr(times))
+    n = lib.oracle_mms_run_q(int(example), int(lat), int(N), float(tau), float(t_end),
+                             int(n_samples), int(nthreads),
+                             -1 if quad_axes is None else int(quad_axes), _ptr(errs),
+                             _ptr(times))
     if n < 0:
         raise ValueError("oracle_mms_run failed with status %d" % n)
     return errs, times, int(n)

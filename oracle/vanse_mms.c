@@ -224,8 +224,19 @@ int oracle_mms_force_exact(int ex, const double X[3], double t, double nu, doubl
  * per node) and of the mean-free pressure, both in physical units, and
  * times the sample times.  Returns the number of steps run, or < 0.
  * ------------------------------------------------------------------------ */
+int64_t oracle_mms_run_q(int ex, int lattice, int N, double tau, double t_end, int n_samples,
+                         int nthreads, int quad_override, double *errs, double *times);
+
 int64_t oracle_mms_run(int ex, int lattice, int N, double tau, double t_end, int n_samples,
                        int nthreads, double *errs, double *times)
+{
+    return oracle_mms_run_q(ex, lattice, N, tau, t_end, n_samples, nthreads, -1, errs, times);
+}
+
+/* As oracle_mms_run; quad_override >= 0 replaces the example's quadrature
+ * axes (8 = no cell-integral correction, the ablation). */
+int64_t oracle_mms_run_q(int ex, int lattice, int N, double tau, double t_end, int n_samples,
+                         int nthreads, int quad_override, double *errs, double *times)
 {
     int dim, quad, transient;
     int64_t dims[3], ncells, cell, nsteps, n;
@@ -236,6 +247,7 @@ int64_t oracle_mms_run(int ex, int lattice, int N, double tau, double t_end, int
     int q, k, next_sample = 1, rc = 0;
 
     if (oracle_mms_info(ex, &dim, &quad, &transient) != 0) return -1;
+    if (quad_override >= 0) quad = quad_override;
     if (dim == 2 && lattice != 0) return -1;
     if (dim == 3 && lattice == 0) return -1;
     if (N < 2 || n_samples < 1 || !(tau > 0.5)) return -1;

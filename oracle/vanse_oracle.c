@@ -127,10 +127,16 @@ int oracle_quad_weights(int n_axes, double *w0, double *wi)
 
 static int popcount3(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1); }
 
+/* quad_axes == OR_QUAD_NONE: no cell integral, I = phi, i.e. the density
+ * sum f / phi of the earlier VANSE schemes the paper corrects (used only to
+ * show what the correction changes). */
+#define OR_QUAD_NONE 8
+
 static int or_check(const or_lattice *L, const int64_t dims[3], int quad_axes)
 {
     if (dims[0] < 1 || dims[1] < 1 || dims[2] < 1) return OR_EINVAL;
     if (L->d == 2 && dims[2] != 1) return OR_EINVAL;
+    if (quad_axes == OR_QUAD_NONE) return OR_OK;
     if (quad_axes < 0 || quad_axes > 7) return OR_EINVAL;
     if (L->d == 2 && (quad_axes & 4)) return OR_EINVAL;
     return OR_OK;
@@ -160,7 +166,7 @@ static void or_eps_ops(const or_lattice *L, const int64_t dims[3], const double 
     const double e = eps[cell];
     double ep[3], em[3];
     double S = 0.0, wi, w0;
-    int a, n_axes = popcount3(quad_mask);
+    int a, n_axes = popcount3(quad_mask & 7);
 
     ep[0] = eps[(z * ny + y) * nx + wrap(x + 1, nx)];
     em[0] = eps[(z * ny + y) * nx + wrap(x - 1, nx)];
@@ -175,8 +181,12 @@ static void or_eps_ops(const or_lattice *L, const int64_t dims[3], const double 
             S = S + em[a];
         }
     }
-    oracle_quad_weights(n_axes, &w0, &wi);
-    *I = e + wi * (S - (double)(2 * n_axes) * e);
+    if (quad_mask == OR_QUAD_NONE)
+        *I = e;
+    else {
+        oracle_quad_weights(n_axes, &w0, &wi);
+        *I = e + wi * (S - (double)(2 * n_axes) * e);
+    }
 
     for (a = 0; a < 3; ++a) g[a] = (a < L->d) ? 0.5 * (ep[a] - em[a]) : 0.0;
 }

@@ -60,11 +60,13 @@ StepArgs step_args(const Solver &s, int64_t n)
     a.omega = 1.0 / s.tau;
     a.fcoef = 1.0 - 0.5 * a.omega;
     for (int d = 0; d < 3; ++d) a.F[d] = s.F[d];
+    a.force = s.force_on ? s.force : nullptr;
     int n_axes = 0;
     for (int b = 0; b < 3; ++b) n_axes += (s.qmask >> b) & 1;
-    a.wq = quad_weight(n_axes);
+    // VANSE_QUAD_NONE: no cell-integral correction, I = phi (ablation)
+    a.wq = n_axes ? quad_weight(n_axes) : 0.0;
     a.n2 = 2.0 * n_axes;
-    a.qmask = s.qmask;
+    a.qmask = s.qmask & 7;
     a.flags = s.flags;
     a.block = (unsigned)(s.tile_x * s.tile_y);
     a.row = (s.allow_row && s.geo.nx % s.tile_x == 0 && s.geo.ny % s.tile_y == 0) ? 1 : 0;
@@ -105,6 +107,9 @@ int hip_fail(Solver *s, hipError_t e, const char *where)
     return fail(s, VANSE_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// threads per block the step kernel of the lattice is compiled for
+int max_threads(const Solver &s) { return s.lattice == VANSE_D3Q27 ? 256 : 1024; }
+
 size_t elem_bytes(int mode)
 {
     return mode == vanse::MODE_F64 ? 8 : (mode == vanse::MODE_F32S ? 4 : 2);
@@ -118,7 +123,7 @@ int vanse_create(int lattice, const int64_t dims[3], double tau, int dtype, vans
 {
     if (!out) return fail(nullptr, VANSE_EINVAL, "vanse_create: out is NULL");
     *out = nullptr;
-    if (lattice != VANSE_D2Q9 && lattice != VANSE_D3Q19)
+    if (lattice != VANSE_D2Q9 && lattice != VANSE_D3Q19 && lattice != VANSE_D3Q27)
         return fail(nullptr, VANSE_EINVAL, "vanse_create: unknown lattice");
     if (dtype != VANSE_FP64 && dtype != VANSE_FP32_SHIFTED && dtype != VANSE_FP16_SHIFTED)
         return fail(nullptr, VANSE_EINVAL, "vanse_create: unknown dtype");
@@ -140,7 +145,7 @@ int vanse_create(int lattice, const int64_t dims[3], double tau, int dtype, vans
     s.lattice = lattice;
     s.mode = dtype;
     s.d = lattice == VANSE_D2Q9 ? 2 : 3;
-    s.q = lattice == VANSE_D2Q9 ? 9 : 19;
+    s.q = lattice == VANSE_D2Q9 ? 9 : (lattice == VANSE_D3Q19 ? 19 : 27);
     s.geo.nx = (int)dims[0];
     s.geo.ny = (int)dims[1];
     s.geo.nz = (int)dims[2];
@@ -177,6 +182,7 @@ int vanse_destroy(vanse_t h)
     (void)hipFree(s.f);
     (void)hipFree(s.pert);
     (void)hipFree(s.scratch);
+    (void)hipFree(s.force);
     delete h;
     return VANSE_OK;
 }
@@ -195,7 +201,7 @@ int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, doubl
     Solver &s = h->s;
     if (!std::isfinite(eps_mean) || !std::isfinite(period))
         return fail(&s, VANSE_EINVAL, "vanse_set_porosity: eps_mean and period must be finite");
-    if (quad_axes < 0 || quad_axes > 7 || (s.d == 2 && (quad_axes & 4)))
+    if (quad_axes != VANSE_QUAD_NONE && (quad_axes < 0 || quad_axes > 7 || (s.d == 2 && (quad_axes & 4))))
         return fail(&s, VANSE_EINVAL, "vanse_set_porosity: bad quad_axes mask");
     hipError_t e;
     if (eps_pert) {
@@ -244,7 +250,7 @@ int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, doubl
     }
     s.eps_mean = eps_mean;
     s.period = period;
-    s.qmask = quad_axes == 0 ? (s.d == 2 ? 3 : 7) : quad_axes;
+    s.qmask = quad_axes == 0 ? (s.d == 2 ? 3 : 7) : (quad_axes == VANSE_QUAD_NONE ? 0 : quad_axes);
     s.porosity_set = true;
     return VANSE_OK;
 }
@@ -260,6 +266,38 @@ int vanse_set_force(vanse_t h, const double F[3])
             return fail(&s, VANSE_EINVAL, "vanse_set_force: z force on a 2-D lattice");
     }
     for (int a = 0; a < 3; ++a) s.F[a] = F[a];
+    return VANSE_OK;
+}
+
+int vanse_set_force_field(vanse_t h, const double *F)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_set_force_field: NULL handle");
+    Solver &s = h->s;
+    if (!F) {
+        s.force_on = false;
+        return VANSE_OK;
+    }
+    const size_t elem = s.mode == vanse::MODE_F64 ? 8 : 4;
+    hipError_t e;
+    if (!s.force) {
+        s.force_bytes = (size_t)s.d * (size_t)s.geo.stride * elem;
+        if ((e = hipMalloc(&s.force, s.force_bytes)) != hipSuccess) {
+            s.force = nullptr;
+            (void)hipGetLastError();
+            return fail(&s, VANSE_ENOMEM, std::string("vanse_set_force_field: ") + hipGetErrorString(e));
+        }
+    }
+    for (int d = 0; d < s.d; ++d) {
+        const double *src = F + (size_t)d * s.geo.ncells;
+        char *dst = static_cast<char *>(s.force) + (size_t)d * s.geo.stride * elem;
+        if (s.mode == vanse::MODE_F64)
+            e = hipMemcpyAsync(dst, src, sizeof(double) * s.geo.ncells, hipMemcpyDeviceToDevice,
+                               s.stream);
+        else
+            e = vanse::launch_convert(src, reinterpret_cast<float *>(dst), s.geo.ncells, s.stream);
+        if (e != hipSuccess) return hip_fail(&s, e, "vanse_set_force_field");
+    }
+    s.force_on = true;
     return VANSE_OK;
 }
 
@@ -340,6 +378,8 @@ int vanse_set_tuning(vanse_t h, int block, int flags)
     Solver &s = h->s;
     if (block != 64 && block != 128 && block != 256 && block != 512 && block != 1024)
         return fail(&s, VANSE_EINVAL, "vanse_set_tuning: block must be 64, 128, 256, 512 or 1024");
+    if (block > max_threads(s))
+        return fail(&s, VANSE_EINVAL, "vanse_set_tuning: D3Q27 blocks are limited to 256 threads");
     if (flags & ~(VANSE_TUNE_NONTEMPORAL | VANSE_TUNE_XCD_REMAP | VANSE_TUNE_FLAT |
                   VANSE_TUNE_NT_STORES))
         return fail(&s, VANSE_EINVAL, "vanse_set_tuning: unknown flag");
@@ -356,8 +396,9 @@ int vanse_set_tile(vanse_t h, int tile_x, int tile_y)
     Solver &s = h->s;
     if (tile_x < 64 || tile_x > 1024 || (tile_x & (tile_x - 1)))
         return fail(&s, VANSE_EINVAL, "vanse_set_tile: tile_x must be a power of two in [64, 1024]");
-    if (tile_y < 1 || tile_x * tile_y > 1024)
-        return fail(&s, VANSE_EINVAL, "vanse_set_tile: tile_x * tile_y must be <= 1024");
+    if (tile_y < 1 || tile_x * tile_y > max_threads(s))
+        return fail(&s, VANSE_EINVAL,
+                    "vanse_set_tile: tile_x * tile_y must be <= 1024 (256 for D3Q27)");
     s.tile_x = tile_x;
     s.tile_y = tile_y;
     return VANSE_OK;
@@ -408,6 +449,7 @@ int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int
         for (int c = 0; c < 6 && rc == VANSE_OK; ++c) {
             const bool tiled_ok = s.geo.nx % cand[c][0] == 0 && s.geo.ny % cand[c][1] == 0;
             if (!cand[c][2] && !tiled_ok) continue;  // would fall back to a flat launch
+            if (cand[c][0] * cand[c][1] > max_threads(s)) continue;
             s.tile_x = cand[c][0];
             s.tile_y = cand[c][1];
             s.allow_row = !cand[c][2];
@@ -453,7 +495,7 @@ int vanse_device_bytes(vanse_t h, int64_t *bytes)
 {
     if (!h || !bytes)
         return fail(h ? &h->s : nullptr, VANSE_EINVAL, "vanse_device_bytes: NULL argument");
-    *bytes = (int64_t)(h->s.f_bytes + h->s.pert_bytes + h->s.scratch_bytes);
+    *bytes = (int64_t)(h->s.f_bytes + h->s.pert_bytes + h->s.scratch_bytes + h->s.force_bytes);
     return VANSE_OK;
 }
 
@@ -464,7 +506,7 @@ const char *vanse_last_error(vanse_t h)
 
 int vanse_lattice_info(int lattice, int *d, int *q, int *xi, double *w)
 {
-    if (lattice != VANSE_D2Q9 && lattice != VANSE_D3Q19)
+    if (lattice != VANSE_D2Q9 && lattice != VANSE_D3Q19 && lattice != VANSE_D3Q27)
         return fail(nullptr, VANSE_EINVAL, "vanse_lattice_info: unknown lattice");
     auto fill = [&](auto lat) {
         using L = decltype(lat);
@@ -481,8 +523,10 @@ int vanse_lattice_info(int lattice, int *d, int *q, int *xi, double *w)
     };
     if (lattice == VANSE_D2Q9)
         fill(vanse::D2Q9{});
-    else
+    else if (lattice == VANSE_D3Q19)
         fill(vanse::D3Q19{});
+    else
+        fill(vanse::D3Q27{});
     return VANSE_OK;
 }
 

@@ -46,6 +46,7 @@ struct StepArgs {
     double omega;        // 1 / tau
     double fcoef;        // 1 - omega / 2 (Guo forcing prefactor)
     double F[3];         // constant external force density
+    const void *force;   // optional per-cell force density, SoA [d][stride] (R), or null
     double wq;           // quadrature weight varpi_{i != 0}
     double n2;           // 2 * (number of quadrature axes)
     int qmask;           // quadrature axes bitmask
@@ -85,6 +86,9 @@ struct Solver {
     size_t f_bytes = 0;
     void *pert = nullptr;        // phi perturbation (double or float)
     size_t pert_bytes = 0;
+    void *force = nullptr;       // per-cell force density (double or float), optional
+    size_t force_bytes = 0;
+    bool force_on = false;
     double *scratch = nullptr;   // reduction partials + results
     size_t scratch_bytes = 0;
     hipStream_t stream = nullptr;
@@ -109,6 +113,7 @@ hipError_t launch_moments(const Solver &s, int parity, double m, double *rho, do
 hipError_t launch_populations(const Solver &s, int parity, double *f);
 hipError_t launch_diagnostics(const Solver &s, int parity, double m, double *out_dev);
 hipError_t launch_convert_pert(const Solver &s, const double *src);
+hipError_t launch_convert(const double *src, float *dst, long long n, hipStream_t st);
 hipError_t launch_pert_range(const Solver &s, double *out_dev);
 hipError_t launch_copy_probe(void *dst, const void *src, int64_t bytes, hipStream_t st);
 

@@ -18,6 +18,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -331,8 +332,15 @@ __device__ __forceinline__ void cell_step(const StepArgs &a, int x, int y, int z
     R I, gx, gy, gz;
     eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
 
-    collide<L, MODE, R>(v, I, gx, gy, gz, R(a.omega), R(a.fcoef), R(a.F[0]), R(a.F[1]),
-                        R(a.F[2]));
+    R Fex = R(a.F[0]), Fey = R(a.F[1]), Fez = R(a.F[2]);
+    if (a.force) {  // per-cell force density, SoA [d][stride] (wave-uniform branch)
+        const R *__restrict__ fc = static_cast<const R *>(a.force);
+        const unsigned off = (unsigned)X[1] * (unsigned)sizeof(R);
+        Fex = Fex + ld<R, false>(fc + (Zo[1] + Yo[1]), off);
+        Fey = Fey + ld<R, false>(fc + a.geo.stride + (Zo[1] + Yo[1]), off);
+        if constexpr (L::D == 3) Fez = Fez + ld<R, false>(fc + 2 * a.geo.stride + (Zo[1] + Yo[1]), off);
+    }
+    collide<L, MODE, R>(v, I, gx, gy, gz, R(a.omega), R(a.fcoef), Fex, Fey, Fez);
 
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
@@ -352,8 +360,14 @@ __device__ __forceinline__ void cell_step(const StepArgs &a, int x, int y, int z
 // and divided with launch-invariant multipliers.
 // XCD remap (flags & 2): the hardware deals blocks round-robin over the 8
 // XCDs; the remap gives each XCD one contiguous range of blocks.
+// Blocks of up to 1024 threads, except D3Q27 (27 populations per thread in
+// registers), whose blocks are capped at 256 threads so that the compiler
+// may hold them without spilling.
+template <class L>
+constexpr int max_block() { return L::Q > 19 ? 256 : 1024; }
+
 template <class L, int MODE, int PARITY, bool ROW, int NT>
-__global__ void __launch_bounds__(1024) step_kernel(StepArgs a)
+__global__ void __launch_bounds__(max_block<L>()) step_kernel(StepArgs a)
 {
     unsigned b = blockIdx.x;
     if (a.flags & 2) {
@@ -453,9 +467,14 @@ __device__ __forceinline__ void macro_f64(const StepArgs &a, const Cell &k, int 
     });
     rho = M0 / I;
     p = rho / 3.0;
+    double Fc[3] = {0.0, 0.0, 0.0};
+    if (a.force) {
+        const R *fc = static_cast<const R *>(a.force);
+        for (int d = 0; d < L::D; ++d) Fc[d] = double(fc[d * a.geo.stride + k.c]);
+    }
     for (int d = 0; d < 3; ++d) {
         if (d < L::D) {
-            F[d] = p * g[d] + a.F[d];
+            F[d] = p * g[d] + (a.F[d] + Fc[d]);
             u[d] = (j[d] + 0.5 * F[d]) / M0;
         } else {
             F[d] = 0.0;
@@ -643,14 +662,14 @@ static inline unsigned blocks_for(long long n, int threads)
 template <class Fn>
 static hipError_t dispatch(int lattice, int mode, Fn &&fn)
 {
-    if (lattice == 0) {
-        if (mode == MODE_F64) return fn(D2Q9{}, std::integral_constant<int, MODE_F64>{});
-        if (mode == MODE_F32S) return fn(D2Q9{}, std::integral_constant<int, MODE_F32S>{});
-        return fn(D2Q9{}, std::integral_constant<int, MODE_F16S>{});
-    }
-    if (mode == MODE_F64) return fn(D3Q19{}, std::integral_constant<int, MODE_F64>{});
-    if (mode == MODE_F32S) return fn(D3Q19{}, std::integral_constant<int, MODE_F32S>{});
-    return fn(D3Q19{}, std::integral_constant<int, MODE_F16S>{});
+    auto by_mode = [&](auto lat) {
+        if (mode == MODE_F64) return fn(lat, std::integral_constant<int, MODE_F64>{});
+        if (mode == MODE_F32S) return fn(lat, std::integral_constant<int, MODE_F32S>{});
+        return fn(lat, std::integral_constant<int, MODE_F16S>{});
+    };
+    if (lattice == 0) return by_mode(D2Q9{});
+    if (lattice == 1) return by_mode(D3Q19{});
+    return by_mode(D3Q27{});
 }
 
 hipError_t launch_step(const Solver &s, const StepArgs &a, int parity)
@@ -759,6 +778,15 @@ hipError_t launch_convert_pert(const Solver &s, const double *src)
 {
     convert_pert_kernel<<<blocks_for(s.geo.ncells, 256), 256, 0, s.stream>>>(
         src, static_cast<float *>(s.pert), s.geo.ncells);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(const double *src, float *dst, long long n, hipStream_t st)
+{
+    for (long long off = 0; off < n; off += (1ll << 30)) {
+        const int m = (int)std::min<long long>(n - off, 1ll << 30);
+        convert_pert_kernel<<<blocks_for(m, 256), 256, 0, st>>>(src + off, dst + off, m);
+    }
     return hipGetLastError();
 }
 

@@ -20,11 +20,12 @@ import torch  # loads the HIP runtime the library binds to (same soname)
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvanse.so")
 
-D2Q9, D3Q19 = 0, 1
+D2Q9, D3Q19, D3Q27 = 0, 1, 2
+QUAD_NONE = 8
 FP64, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
 DTYPES = {"fp64": FP64, "fp32_shifted": FP32_SHIFTED, "fp16_shifted": FP16_SHIFTED}
-LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19}
+LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D3Q27": D3Q27}
 
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE",
            EUNSTABLE: "EUNSTABLE"}
@@ -34,7 +35,7 @@ EXPORTS = [
     "vanse_set_force", "vanse_init", "vanse_step", "vanse_moments", "vanse_diagnostics",
     "vanse_populations", "vanse_time", "vanse_device_bytes", "vanse_last_error",
     "vanse_lattice_info", "vanse_copy_probe", "vanse_set_tuning", "vanse_set_tile",
-    "vanse_autotune",
+    "vanse_autotune", "vanse_set_force_field",
     "vanse_batch_create", "vanse_batch_destroy", "vanse_batch_set_stream",
     "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
     "vanse_batch_last_error",
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
             "vanse_copy_probe": (i, [P, P, i64, P]),
             "vanse_set_tuning": (i, [P, i, i]),
             "vanse_set_tile": (i, [P, i, i]),
+            "vanse_set_force_field": (i, [P, P]),
             "vanse_autotune": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i),
                                    ctypes.POINTER(i), I64P]),
             "vanse_batch_create": (i, [ctypes.POINTER(P), i, ctypes.POINTER(P)]),
@@ -155,7 +157,7 @@ class Solver:
         self.lattice, self.dtype, self.tau = lattice, dtype, float(tau)
         self.dims = tuple(int(v) for v in dims)
         self.d = 2 if lattice == D2Q9 else 3
-        self.q = 9 if lattice == D2Q9 else 19
+        self.q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}[lattice]
         self.ncells = self.dims[0] * self.dims[1] * self.dims[2]
         self.device = torch.device("cuda", torch.cuda.current_device())
         h = ctypes.c_void_p()
@@ -217,6 +219,14 @@ class Solver:
         self._check(self.lib.vanse_autotune(self.h, int(steps_per_trial), ctypes.byref(bx),
                                             ctypes.byref(by), ctypes.byref(fl), ctypes.byref(n)))
         return bx.value, by.value, fl.value, n.value
+
+    def set_force_field(self, F=None):
+        """Per-cell force density, FP64 [d, ncells] (None switches it off)."""
+        self._bind_stream()
+        if F is not None:
+            F = F.to(self.device, torch.float64).contiguous().view(self.d, self.ncells)
+            self._keep_force = F  # alive until the copy has run
+        self._check(self.lib.vanse_set_force_field(self.h, _ptr(F)))
 
     def set_force(self, F):
         F = list(F) + [0.0] * (3 - len(F))

@@ -89,3 +89,15 @@ def test_library_lattice_matches_oracle_by_velocity(name, lat_lib, lat_or):
     H = (len(xi) - 1) // 2
     for i in range(1, H + 1):
         assert np.array_equal(-np.array(xi[i]), np.array(xi[i + H]))
+
+
+def test_library_d3q27_matches_paper_table2():
+    from paper_2208_09267_amd import vanse
+    d, xi, w = vanse.lattice_info(vanse.D3Q27)
+    d_o, c_o, w_o = oracle.lattice(oracle.D3Q27)
+    lut = {tuple(int(v) for v in c): wi for c, wi in zip(c_o, w_o)}
+    assert d == 3 and len(xi) == 27
+    for c, wi in zip(xi, w):
+        assert lut[tuple(c)] == wi
+    for i in range(1, 14):
+        assert np.array_equal(-np.array(xi[i]), np.array(xi[i + 13]))

@@ -1,0 +1,158 @@
+"""GPU tests of the paper's own 3-D lattice (D3Q27), the per-cell force field
+and the ablation without the cell-integral correction, each against the CPU
+oracle; and the paper's convergence claim on the GPU at resolutions the CPU
+oracle cannot reach in a test (manufactured solutions, FP64)."""
+import zlib
+
+import numpy as np
+import pytest
+import torch
+
+import mms_fields as M
+import oracle
+from gpu_helpers import rel_linf
+from paper_2208_09267_amd import vanse
+
+pytestmark = pytest.mark.gpu
+
+LAT = {"D2Q9": (vanse.D2Q9, oracle.D2Q9), "D3Q19": (vanse.D3Q19, oracle.D3Q19),
+       "D3Q27": (vanse.D3Q27, oracle.D3Q27)}
+
+
+def _perm(lat):
+    _, xi, _ = vanse.lattice_info(LAT[lat][0])
+    _, c_o, _ = oracle.lattice(LAT[lat][1])
+    lut = {tuple(v): i for i, v in enumerate(xi)}
+    return np.array([lut[tuple(int(a) for a in c)] for c in c_o])
+
+
+def _case(lat, dims, seed, force_field=False, quad=0):
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(dims))
+    d = 2 if lat == "D2Q9" else 3
+    c = dict(tau=float(rng.uniform(0.52, 1.2)), eps_mean=0.7, pert=rng.uniform(-0.2, 0.2, n),
+             period=float(rng.uniform(9, 30)), u0=rng.uniform(-0.04, 0.04, (d, n)),
+             rho0=rng.uniform(0.97, 1.03, n), quad=quad,
+             force=(2e-5, -1e-5, 3e-5 if d == 3 else 0.0))
+    c["field"] = rng.uniform(-1e-4, 1e-4, (3, n)) if force_field else None
+    if c["field"] is not None and d == 2:
+        c["field"][2] = 0.0
+    return c
+
+
+def _compare(lat, dims, steps, c):
+    d = 2 if lat == "D2Q9" else 3
+    s = vanse.Solver(LAT[lat][0], dims, c["tau"], vanse.FP64)
+    s.set_porosity(c["eps_mean"], torch.from_numpy(c["pert"]).cuda(), c["period"], c["quad"])
+    s.set_force(c["force"])
+    if c["field"] is not None:
+        s.set_force_field(torch.from_numpy(np.ascontiguousarray(c["field"][:d])).cuda())
+    s.init(torch.from_numpy(c["rho0"]).cuda(), torch.from_numpy(c["u0"]).cuda())
+    s.step(steps)
+    f_gpu = s.populations().cpu().numpy()
+    rho, p, u = (t.cpu().numpy() for t in s.moments())
+    s.close()
+    olat = LAT[lat][1]
+    eps0 = oracle.eps_at(dims, c["eps_mean"], c["pert"], c["period"], 0)
+    f = oracle.init(olat, dims, eps0, c["rho0"], c["u0"])
+    f, eps = oracle.run_separable(olat, dims, c["tau"], c["eps_mean"], c["pert"], c["period"],
+                                  f, 0, steps, quad_axes=c["quad"], force=c["field"],
+                                  fext=c["force"])
+    rho_o, p_o, u_o = oracle.moments(olat, dims, eps, f, quad_axes=c["quad"], force=c["field"],
+                                     fext=c["force"])
+    perm = _perm(lat)
+    for k in range(f.shape[1]):
+        assert rel_linf(f_gpu[perm[k]], f[:, k]) <= 1e-12, k
+    for a, b in ((rho, rho_o), (p, p_o), (u, u_o)):
+        assert rel_linf(a, b) <= 1e-12
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 2, 2), (5, 4, 3), (9, 7, 5), (33, 6, 5)])
+@pytest.mark.parametrize("steps", [1, 2, 31])
+def test_d3q27_every_population_vs_oracle(dims, steps):
+    _compare("D3Q27", dims, steps, _case("D3Q27", dims, zlib.crc32(repr(dims).encode()) % 97))
+
+
+@pytest.mark.parametrize("lat,dims", [("D2Q9", (7, 5, 1)), ("D3Q19", (6, 5, 4)),
+                                      ("D3Q27", (5, 4, 3)), ("D3Q19", (40, 9, 7))])
+@pytest.mark.parametrize("steps", [1, 24])
+def test_per_cell_force_field_vs_oracle(lat, dims, steps):
+    _compare(lat, dims, steps, _case(lat, dims, 3, force_field=True))
+
+
+@pytest.mark.parametrize("lat,dims", [("D2Q9", (9, 6, 1)), ("D3Q19", (6, 5, 4)),
+                                      ("D3Q27", (5, 4, 3))])
+def test_ablation_without_cell_integral_vs_oracle(lat, dims):
+    _compare(lat, dims, 17, _case(lat, dims, 4, quad=vanse.QUAD_NONE))
+
+
+@pytest.mark.parametrize("dtype,tol", [(vanse.FP32_SHIFTED, 1e-5), (vanse.FP16_SHIFTED, 2e-2)])
+def test_d3q27_reduced_storage_close_to_fp64(dtype, tol):
+    dims = (24, 20, 16)
+    from paper_2208_09267_amd import workloads as W
+    pert = torch.from_numpy(W.fourier_eps(dims, seed=2)).cuda()
+    u0 = torch.from_numpy(np.ascontiguousarray(W.taylor_green(dims, 0.02))).cuda()
+    out = []
+    for dt in (vanse.FP64, dtype):
+        s = vanse.Solver("D3Q27", dims, 0.6, dt)
+        s.set_porosity(0.75, pert, 50.0)
+        s.init(None, u0)
+        s.step(60)
+        out.append([t.cpu().numpy() for t in s.moments()])
+        s.close()
+    (r64, p64, u64), (r, p, u) = out
+    assert np.abs(u - u64).max() <= tol * np.abs(u64).max()
+    assert np.abs((p - p.mean()) - (p64 - p64.mean())).max() <= tol * np.abs(p64 - p64.mean()).max()
+
+
+def _gpu_mms(ex, N, tau, t_end, quad=None):
+    """Stationary manufactured solution on the GPU (FP64): returns the
+    stabilised errors [u L1, L2, Linf, p L1, L2, Linf] in physical units."""
+    dims, phi, u, p, F = M.mms_arrays(ex, N, 0.0)
+    d = 3 if ex in (2, 5) else 2
+    lat = "D3Q19" if d == 3 else "D2Q9"
+    dx = 2.0 / N
+    dt = (tau - 0.5) / 3.0 * dx * dx / 0.1
+    us, ps, fs = dt / dx, (dt / dx) ** 2, dt * dt / dx
+    nsteps = int(round(t_end / dt))
+    s = vanse.Solver(lat, dims, tau, vanse.FP64)
+    s.set_porosity(0.0, torch.from_numpy(phi).cuda(), 0.0, 0 if quad is None else quad)
+    s.set_force_field(torch.from_numpy(np.ascontiguousarray(F[:d] * fs)).cuda())
+    s.init(torch.from_numpy(1.0 + 3.0 * p * ps).cuda(),
+           torch.from_numpy(np.ascontiguousarray(u[:d] * us)).cuda())
+    errs = []
+    for chunk in (nsteps // 2, nsteps - nsteps // 2):
+        s.step(chunk)
+        rho, pl, ul = (t.cpu().numpy() for t in s.moments())
+        du = np.sqrt(((ul / us - u[:d]) ** 2).sum(0))
+        dp = np.abs((pl - pl.mean()) / ps - (p - p.mean()))
+        errs.append([du.mean(), np.sqrt((du ** 2).mean()), du.max(),
+                     dp.mean(), np.sqrt((dp ** 2).mean()), dp.max()])
+    s.close()
+    errs = np.array(errs)
+    assert np.all(np.abs(errs[1] - errs[0]) <= 0.05 * errs[1]), errs  # stabilised
+    return errs[1]
+
+
+def test_example1_second_order_on_gpu_to_n128():
+    e = np.array([_gpu_mms(1, N, 0.53, 16.0) for N in (32, 64, 128)])
+    print("Ex.1 GPU errors", e)
+    for k in range(2):
+        eoc = np.log2(e[k] / e[k + 1])
+        assert np.all(eoc > 1.8) and np.all(eoc < 2.2), eoc
+    # the oracle's N = 32 errors (same physics on the CPU)
+    o = oracle.mms_run(1, 32, 0.53, 16.0, n_samples=1, nthreads=1)[0][0]
+    np.testing.assert_allclose(e[0], o, rtol=1e-4)
+
+
+def test_example1_ablation_pressure_does_not_converge_on_gpu():
+    e = np.array([_gpu_mms(1, N, 0.53, 16.0, quad=vanse.QUAD_NONE) for N in (64, 128)])
+    eoc = np.log2(e[0] / e[1])
+    assert np.all(eoc[:3] > 1.8) and np.all(np.abs(eoc[3:]) < 0.2), eoc
+
+
+def test_example2_second_order_on_gpu_to_n64():
+    e = np.array([_gpu_mms(2, N, 0.53, 16.0) for N in (16, 32, 64)])
+    print("Ex.2 GPU errors", e)
+    eoc = np.log2(e[1] / e[2])
+    assert np.all(eoc > 1.7) and np.all(eoc < 2.3), eoc
