@@ -258,6 +258,22 @@ def precision_study():
     out = {"workload": w.name, "steps": w.steps,
            "reference": "GPU FP64 (matches the CPU oracle to <= 1e-11 relative Linf)",
            "discretisation": {k: norms(v) for k, v in disc.items()}, "modes": {}}
+    gold = os.path.join(ROOT, "tests", "golden", "d3q19_256.npz")
+    if os.path.exists(gold):
+        import numpy as np
+
+        g = np.load(gold)
+        cells = torch.from_numpy(g["cells"]).cuda()
+        vs = {}
+        for name, (r, p, u) in ref.items():
+            vs[name] = {"rho": float((r[cells].cpu().numpy() - g["rho"]).__abs__().max()),
+                        "p": float((p[cells].cpu().numpy() - g["p"]).__abs__().max()),
+                        "u": float((u[:, cells].cpu().numpy() - g["u"]).__abs__().max())}
+        out["vs_cpu_oracle_samples_linf"] = {
+            "cells": int(len(g["cells"])), "oracle_field_linf": {"rho": float(g["norms"][0]),
+                                                                 "p": float(g["norms"][1]),
+                                                                 "u": float(g["norms"][2])},
+            "abs_error": vs}
     for name in ("fp32_shifted", "fp16_shifted"):
         r, p, u = ref[name]
         err = {"rho": r - r64, "p": p - p64, "u": (u - u64).norm(dim=0),
@@ -298,7 +314,8 @@ def serve_run(rate, duration, budget, cell_cap, seed=4):
     out.update({"rate_per_s": rate, "arrival_window_s": duration,
                 "offered_glups": offered / 1e9, "hbm_budget_gb": budget / 1e9,
                 "cell_cap": cell_cap, "batch_rebuilds": srv.stats["rebuilds"],
-                "chunks": srv.stats["chunks"]})
+                "chunks": srv.stats["chunks"],
+                "loop_seconds": {k: round(v, 2) for k, v in srv.time.items()}})
     return out
 
 

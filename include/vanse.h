@@ -174,6 +174,12 @@ typedef struct vanse_batch *vanse_batch_t;
  * ESTATE, ENOMEM, EDEVICE. */
 int vanse_batch_create(const vanse_t *solvers, int count, vanse_batch_t *out);
 
+/* Replace the members of b by `count` other (or the same) solvers of the
+ * same lattice and dtype, keeping b's tuning and reusing its device tables
+ * (grown when needed).  For request loops whose membership changes often.
+ * Synchronises b's stream first.  Errors as vanse_batch_create. */
+int vanse_batch_update(vanse_batch_t b, const vanse_t *solvers, int count);
+
 /* Free the batch's tables and graph (not the solvers).  b may be NULL. */
 int vanse_batch_destroy(vanse_batch_t b);
 

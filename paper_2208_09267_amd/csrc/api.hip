@@ -2,6 +2,7 @@
 // validation, ownership of device memory, time stepping and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -30,11 +31,14 @@ struct vanse_batch {
     unsigned nblocks = 0;
     vanse::BatchMember *d_members = nullptr;
     unsigned *d_owner = nullptr;
-    char *d_tab = nullptr;              // [chunk_cap][count] m values, then [count] t0
+    char *d_tab = nullptr;              // [chunk_cap][cap] m values, then [cap] t0
     char *h_tab[2] = {nullptr, nullptr};  // pinned staging, double buffered
     hipEvent_t tab_done[2] = {nullptr, nullptr};
     int cur = 0;
     int chunk_cap = 0;
+    int cap_count = 0;                  // members the tables are sized for
+    size_t cap_owner = 0;               // blocks the owner table is sized for
+    size_t d_members_cap = 0;           // members the member table is sized for
     hipGraphExec_t gexec = nullptr;
     hipStream_t stream = nullptr;
     std::string err;
@@ -572,7 +576,31 @@ void batch_free(vanse_batch *b)
 
 size_t tab_bytes(const vanse_batch *b)
 {
-    return sizeof(double) * (size_t)b->chunk_cap * b->count + sizeof(long long) * b->count;
+    return sizeof(double) * (size_t)b->chunk_cap * b->cap_count +
+           sizeof(long long) * b->cap_count;
+}
+
+// Size the modulation/time tables and their staging buffers for b->count
+// members (grown geometrically; reused while large enough).
+hipError_t batch_tables(vanse_batch *b)
+{
+    if (b->count <= b->cap_count && b->d_tab) return hipSuccess;
+    for (int k = 0; k < 2; ++k) {
+        if (b->tab_done[k]) (void)hipEventSynchronize(b->tab_done[k]);
+        if (b->h_tab[k]) (void)hipHostFree(b->h_tab[k]);
+        b->h_tab[k] = nullptr;
+    }
+    (void)hipFree(b->d_tab);
+    b->d_tab = nullptr;
+    b->cap_count = std::max(b->count, b->cap_count + b->cap_count / 2);
+    hipError_t e = hipMalloc((void **)&b->d_tab, tab_bytes(b));
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = hipHostMalloc((void **)&b->h_tab[k], tab_bytes(b), hipHostMallocDefault);
+        if (e == hipSuccess && !b->tab_done[k])
+            e = hipEventCreateWithFlags(&b->tab_done[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(b->tab_done[k], b->stream);
+    }
+    return e;
 }
 
 // (Re)build the member and owner tables for the current block size.
@@ -595,14 +623,24 @@ int batch_layout(vanse_batch *b)
         begin += m.nblocks;
     }
     b->nblocks = begin;
-    (void)hipFree(b->d_members);
-    (void)hipFree(b->d_owner);
-    b->d_members = nullptr;
-    b->d_owner = nullptr;
-    hipError_t e;
-    if ((e = hipMalloc((void **)&b->d_members, sizeof(vanse::BatchMember) * b->count)) != hipSuccess ||
-        (e = hipMalloc((void **)&b->d_owner, sizeof(unsigned) * owner.size())) != hipSuccess)
-        return bfail(b, VANSE_ENOMEM, std::string("vanse_batch: hipMalloc: ") + hipGetErrorString(e));
+    hipError_t e = batch_tables(b);
+    if (e != hipSuccess)
+        return bfail(b, VANSE_ENOMEM, std::string("vanse_batch: tables: ") + hipGetErrorString(e));
+    if (!b->d_members || (size_t)b->count > b->d_members_cap) {
+        (void)hipFree(b->d_members);
+        b->d_members = nullptr;
+        b->d_members_cap = (size_t)b->cap_count;
+        if ((e = hipMalloc((void **)&b->d_members, sizeof(vanse::BatchMember) * b->d_members_cap)) !=
+            hipSuccess)
+            return bfail(b, VANSE_ENOMEM, std::string("vanse_batch: hipMalloc: ") + hipGetErrorString(e));
+    }
+    if (!b->d_owner || owner.size() > b->cap_owner) {
+        (void)hipFree(b->d_owner);
+        b->d_owner = nullptr;
+        b->cap_owner = std::max(owner.size(), b->cap_owner + b->cap_owner / 2);
+        if ((e = hipMalloc((void **)&b->d_owner, sizeof(unsigned) * b->cap_owner)) != hipSuccess)
+            return bfail(b, VANSE_ENOMEM, std::string("vanse_batch: hipMalloc: ") + hipGetErrorString(e));
+    }
     if ((e = hipMemcpy(b->d_members, mem.data(), sizeof(vanse::BatchMember) * b->count,
                        hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(b->d_owner, owner.data(), sizeof(unsigned) * owner.size(),
@@ -623,7 +661,7 @@ int batch_upload(vanse_batch *b, int k)
     hipError_t e = hipEventSynchronize(b->tab_done[slot]);  // staging buffer free again
     if (e != hipSuccess) return bfail(b, VANSE_EDEVICE, "vanse_batch_step: event sync failed");
     double *m = reinterpret_cast<double *>(b->h_tab[slot]);
-    long long *t0 = reinterpret_cast<long long *>(m + (size_t)b->chunk_cap * b->count);
+    long long *t0 = reinterpret_cast<long long *>(m + (size_t)b->chunk_cap * b->cap_count);
     for (int s = 0; s < b->count; ++s) {
         const Solver &sv = b->members[s]->s;
         t0[s] = sv.t;
@@ -640,7 +678,7 @@ hipError_t batch_launch(vanse_batch *b, int j, hipStream_t st)
 {
     const double *mtab = reinterpret_cast<const double *>(b->d_tab);
     const long long *t0 =
-        reinterpret_cast<const long long *>(b->d_tab + sizeof(double) * (size_t)b->chunk_cap * b->count);
+        reinterpret_cast<const long long *>(b->d_tab + sizeof(double) * (size_t)b->chunk_cap * b->cap_count);
     return vanse::launch_batch_step(b->lattice, b->mode, b->nt, b->nblocks, (unsigned)b->block,
                                     b->d_members, b->d_owner, mtab, t0, j, b->count, st);
 }
@@ -694,22 +732,37 @@ int batch_run(vanse_batch *b, int64_t n, bool allow_graph)
 
 extern "C" {
 
+}  // extern "C"
+
+namespace {
+int check_members(vanse_batch *b, const vanse_t *solvers, int count, const char *who)
+{
+    if (!solvers || count < 1) return bfail(b, VANSE_EINVAL, std::string(who) + ": no solvers");
+    std::vector<vanse_t> sorted(solvers, solvers + count);
+    std::sort(sorted.begin(), sorted.end());
+    for (int k = 0; k < count; ++k) {
+        if (!solvers[k]) return bfail(b, VANSE_EINVAL, std::string(who) + ": NULL handle");
+        const Solver &s = solvers[k]->s;
+        if (!s.initialized) return bfail(b, VANSE_ESTATE, std::string(who) + ": member not initialised");
+        if (s.lattice != solvers[0]->s.lattice || s.mode != solvers[0]->s.mode)
+            return bfail(b, VANSE_EINVAL, std::string(who) + ": members differ in lattice or dtype");
+        if (k > 0 && sorted[k] == sorted[k - 1])
+            return bfail(b, VANSE_EINVAL, std::string(who) + ": duplicate member");
+    }
+    if (b && (solvers[0]->s.lattice != b->lattice || solvers[0]->s.mode != b->mode))
+        return bfail(b, VANSE_EINVAL, std::string(who) + ": lattice or dtype differs from the batch");
+    return VANSE_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int vanse_batch_create(const vanse_t *solvers, int count, vanse_batch_t *out)
 {
     if (!out) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: out is NULL");
     *out = nullptr;
-    if (!solvers || count < 1) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: no solvers");
-    for (int k = 0; k < count; ++k) {
-        if (!solvers[k]) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: NULL handle");
-        const Solver &s = solvers[k]->s;
-        if (!s.initialized)
-            return bfail(nullptr, VANSE_ESTATE, "vanse_batch_create: member not initialised");
-        if (s.lattice != solvers[0]->s.lattice || s.mode != solvers[0]->s.mode)
-            return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: members differ in lattice or dtype");
-        for (int l = 0; l < k; ++l)
-            if (solvers[l] == solvers[k])
-                return bfail(nullptr, VANSE_EINVAL, "vanse_batch_create: duplicate member");
-    }
+    int crc = check_members(nullptr, solvers, count, "vanse_batch_create");
+    if (crc != VANSE_OK) return crc;
     auto *b = new (std::nothrow) vanse_batch();
     if (!b) return bfail(nullptr, VANSE_ENOMEM, "vanse_batch_create: host allocation failed");
     b->members.assign(solvers, solvers + count);
@@ -718,16 +771,9 @@ int vanse_batch_create(const vanse_t *solvers, int count, vanse_batch_t *out)
     b->mode = solvers[0]->s.mode;
     b->stream = solvers[0]->s.stream;
     b->chunk_cap = 16;
-    hipError_t e = hipSuccess;
-    if ((e = hipMalloc((void **)&b->d_tab, tab_bytes(b))) == hipSuccess)
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-            e = hipHostMalloc((void **)&b->h_tab[k], tab_bytes(b), hipHostMallocDefault);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->tab_done[k], hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventRecord(b->tab_done[k], b->stream);
-        }
-    int rc = (e == hipSuccess) ? batch_layout(b) : VANSE_ENOMEM;
+    int rc = batch_layout(b);
     if (rc != VANSE_OK) {
-        std::string msg = b->err.empty() ? std::string("vanse_batch_create: ") + hipGetErrorString(e) : b->err;
+        std::string msg = b->err;
         batch_free(b);
         delete b;
         (void)hipGetLastError();
@@ -735,6 +781,19 @@ int vanse_batch_create(const vanse_t *solvers, int count, vanse_batch_t *out)
     }
     *out = b;
     return VANSE_OK;
+}
+
+int vanse_batch_update(vanse_batch_t b, const vanse_t *solvers, int count)
+{
+    if (!b) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_update: NULL batch");
+    int rc = check_members(b, solvers, count, "vanse_batch_update");
+    if (rc != VANSE_OK) return rc;
+    // the tables are rewritten below: no launch of this batch may still read them
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, VANSE_EDEVICE, std::string("vanse_batch_update: ") + hipGetErrorString(e));
+    b->members.assign(solvers, solvers + count);
+    b->count = count;
+    return batch_layout(b);
 }
 
 int vanse_batch_destroy(vanse_batch_t b)

@@ -111,6 +111,7 @@ class Server:
         self.log = log
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stats = collections.Counter()
+        self.time = collections.Counter()  # host seconds per loop phase
         self.tuning = (256, 0)
 
     def _start(self, rid, work: W.Workload, now) -> Tuple[Optional[_Active], Result]:
@@ -164,6 +165,7 @@ class Server:
                 res.finish = clock() - t0
                 results[rid] = res
                 continue
+            tadm = clock()
             for _ in range(k):
                 rid, ta, work = queue.popleft()
                 act, res = self._start(rid, work, ta)
@@ -176,14 +178,17 @@ class Server:
                 active.append(act)
                 used += state_bytes(work.lattice, work.dims, self.dtype)
                 dirty = True
+            self.time["admit"] += clock() - tadm
             if not active:
                 if i < len(arrivals) and realtime:
                     time.sleep(max(0.0, arrivals[i][1][0] - (clock() - t0)))
                 continue
             if dirty:
-                if batch is not None:
-                    batch.close()
-                batch = vanse.Batch([a.solver for a in active])
+                tr = clock()
+                if batch is None:
+                    batch = vanse.Batch([a.solver for a in active])
+                else:
+                    batch.update([a.solver for a in active])
                 block, flags = self.tuning
                 if self.autotune:
                     # trial steps are real steps: keep them within every member's count
@@ -196,6 +201,8 @@ class Server:
                 batch.set_tuning(block, flags, self.chunk)
                 dirty = False
                 self.stats["rebuilds"] += 1
+                self.time["rebuild"] += clock() - tr
+            ts = clock()
             step = min(self.chunk, min(a.remaining for a in active))
             if step > 0:
                 batch.step(step)
@@ -203,10 +210,12 @@ class Server:
                     a.remaining -= step
                 self.stats["chunks"] += 1
             torch.cuda.current_stream().synchronize()
+            self.time["step"] += clock() - ts
             done = [a for a in active if a.remaining <= 0]
             if done:
-                batch.close()
-                batch = None
+                tr = clock()
+                # the batch keeps the retired members' pointers until the next
+                # update, but it is not stepped before that
                 dirty = True
                 for a in done:
                     rho, p, u = a.solver.moments()
@@ -222,6 +231,7 @@ class Server:
                     if self.log:
                         self.log(a.result)
                 active = [a for a in active if a.remaining > 0]
+                self.time["retire"] += clock() - tr
         if batch is not None:
             batch.close()
         return [results[r] for r in sorted(results)]

@@ -38,7 +38,7 @@ EXPORTS = [
     "vanse_autotune", "vanse_set_force_field",
     "vanse_batch_create", "vanse_batch_destroy", "vanse_batch_set_stream",
     "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
-    "vanse_batch_last_error",
+    "vanse_batch_last_error", "vanse_batch_update",
 ]
 TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT, TUNE_NT_STORES = 1, 2, 4, 8
 
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
             "vanse_batch_step": (i, [P, i64]),
             "vanse_batch_autotune": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i), I64P]),
             "vanse_batch_last_error": (ctypes.c_char_p, [P]),
+            "vanse_batch_update": (i, [P, ctypes.POINTER(P), i]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -306,6 +307,13 @@ class Batch:
 
     def set_tuning(self, block=256, flags=0, chunk=16):
         self._check(self.lib.vanse_batch_set_tuning(self.h, int(block), int(flags), int(chunk)))
+
+    def update(self, solvers):
+        """Replace the members (same lattice and dtype), reusing the tables."""
+        solvers = list(solvers)
+        arr = (ctypes.c_void_p * len(solvers))(*[s.h.value for s in solvers])
+        self._check(self.lib.vanse_batch_update(self.h, arr, len(solvers)))
+        self.solvers = solvers
 
     def step(self, n=1):
         self._bind_stream()

@@ -88,3 +88,26 @@ def test_batch_rejects_mixed_or_uninitialised_members():
         vanse.Batch([a, a])
     for s in (a, c, u):
         s.close()
+
+
+def test_batch_update_changes_members_and_stays_bitwise():
+    dtype = vanse.FP32_SHIFTED
+    solo = [_make(d, t, s, dtype) for d, t, s in CASES]
+    mem = [_make(d, t, s, dtype) for d, t, s in CASES]
+    b = vanse.Batch(mem[:2])
+    b.step(7)
+    b.update(mem[1:5])          # drop one, add three (different time levels)
+    b.step(20)
+    b.update(mem)               # grow past the first capacity
+    b.step(3)
+    b.update([mem[4]])
+    b.step(5)
+    steps = [10, 30, 23, 23, 28]
+    for s, n in zip(solo, steps):
+        s.step(n)
+    for s, m, n in zip(solo, mem, steps):
+        assert m.time == n
+        assert np.array_equal(s.populations().cpu().numpy(), m.populations().cpu().numpy())
+    b.close()
+    for s in solo + mem:
+        s.close()

@@ -230,3 +230,32 @@ def test_autotune_is_bitwise_neutral_and_counts_its_steps():
     assert b.autotune(2) == (tx, ty, flags, 0)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED])
+def test_d3q19_256_full_run_in_bench_launch_vs_oracle_samples(dtype):
+    """The headline workload (256^3, 2000 steps) in the launch shape the
+    benchmark uses (autotuned during warm-up), against oracle samples:
+    FP64 to 1e-11 relative; FP32 shifted within its storage error."""
+    path = os.path.join(GOLD, "d3q19_256.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle reference d3q19_256.npz not generated")
+    g = np.load(path)
+    w = W.d3q19_256()
+    s = vanse.Solver(w.lattice, w.dims, w.tau, dtype)
+    s.set_porosity(w.eps_mean, torch.from_numpy(w.eps_pert()).cuda(), w.period)
+    s.init(None, torch.from_numpy(np.ascontiguousarray(w.u0())).cuda())
+    _, _, _, ran = s.autotune(4)
+    s.step(w.steps - ran)
+    assert s.time == w.steps
+    rho, p, u = (t.cpu().numpy() for t in s.moments())
+    s.close()
+    cells = g["cells"]
+    e_rho = np.abs(rho[cells] - g["rho"]).max() / g["norms"][0]
+    e_p = np.abs(p[cells] - g["p"]).max() / g["norms"][1]
+    e_u = np.abs(u[:, cells] - g["u"]).max() / g["norms"][2]
+    print("256^3 sampled rel Linf rho %.3e p %.3e u %.3e" % (e_rho, e_p, e_u))
+    if dtype == vanse.FP64:
+        assert e_rho <= 1e-11 and e_p <= 1e-11 and e_u <= 1e-11
+    else:
+        assert e_rho <= 1e-4 and e_p <= 1e-4 and e_u <= 1e-4
