@@ -259,3 +259,49 @@ def test_d3q19_256_full_run_in_bench_launch_vs_oracle_samples(dtype):
         assert e_rho <= 1e-11 and e_p <= 1e-11 and e_u <= 1e-11
     else:
         assert e_rho <= 1e-4 and e_p <= 1e-4 and e_u <= 1e-4
+
+
+def test_largest_grid_equals_replicated_row_bitwise():
+    """Maximum sizes: a 1024^3 lattice (1.07 G cells, 4.3 GB per FP32
+    population plane) whose inputs vary along x only must evolve exactly
+    like the single row 1024 x 1 x 1 at every (y, z): the y/z neighbours
+    of every cell carry the same values, so every cell does the same
+    arithmetic.  Exercises every offset path beyond 2^32 bytes."""
+    nx, big = 1024, (1024, 1024, 1024)
+    x = np.arange(nx)
+    pert_row = 0.2 * np.sin(2 * np.pi * x / nx) * np.cos(6 * np.pi * x / nx)
+    u_row = np.zeros((3, nx))
+    u_row[1] = 0.03 * np.sin(2 * np.pi * x / nx)
+    u_row[0] = 0.01 * np.cos(4 * np.pi * x / nx)
+    out = {}
+    for dims in (big,):
+        reps = dims[1] * dims[2]
+        s = vanse.Solver("D3Q19", dims, 0.62, vanse.FP32_SHIFTED)
+        pert = torch.from_numpy(pert_row).cuda().repeat(reps)
+        s.set_porosity(0.75, pert, 40.0)
+        s.set_force((2e-6, 0.0, 0.0))
+        u0 = torch.from_numpy(u_row).cuda().repeat(1, reps)
+        s.init(None, u0)
+        del pert, u0
+        s.step(3)
+        rho, p, u = s.moments()
+        torch.cuda.synchronize()
+        s.close()
+        rng = np.random.default_rng(5)
+        cells = torch.from_numpy(rng.integers(0, dims[0] * dims[1] * dims[2], 4096)).cuda()
+        cells = torch.cat([cells, torch.tensor([0, dims[0] * dims[1] * dims[2] - 1]).cuda()])
+        out[dims] = (cells.cpu().numpy(), rho[cells].cpu().numpy(), p[cells].cpu().numpy(),
+                     u[:, cells].cpu().numpy())
+        del rho, p, u
+        torch.cuda.empty_cache()
+    cells, rho, p, u = out[big]
+    s = vanse.Solver("D3Q19", (nx, 1, 1), 0.62, vanse.FP32_SHIFTED)
+    s.set_porosity(0.75, torch.from_numpy(pert_row).cuda(), 40.0)
+    s.set_force((2e-6, 0.0, 0.0))
+    s.init(None, torch.from_numpy(u_row).cuda())
+    s.step(3)
+    rr, pp, uu = (t.cpu().numpy() for t in s.moments())
+    s.close()
+    xs = cells % nx
+    assert np.array_equal(rho, rr[xs]) and np.array_equal(p, pp[xs])
+    assert np.array_equal(u, uu[:, xs])
