@@ -9,10 +9,12 @@ FP16 shifted.  One "step" is one full time step of the whole lattice; the
 state is resident in HBM before timing starts.
 
 Prints ONE JSON line (rank 0).  `value` is the headline variant's MLUPS;
-`roofline` describes its step kernel against the 8 TB/s HBM peak using
-algorithmic bytes per lattice update (Q loads + Q stores + one phi value);
-`cpu_baseline` times the FP64 CPU oracle on a bounded number of steps of the
-same workload on the host cores.
+`roofline` describes the kernel that runs the steps (the single-step kernel,
+or the two-step kernel when the autotuner picks it) against the 8 TB/s HBM
+peak using its algorithmic bytes per launch: every population loaded once and
+stored once plus one phi value per cell (a two-step launch does two lattice
+updates per cell for those bytes); `cpu_baseline` times the FP64 CPU oracle
+on a bounded number of steps of the same workload on the host cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -28,13 +30,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS and % HBM roofline, D3Q19 256³ FP64 vs FP32-shifted; p50/p99 solve latency"
 PEAK_HBM_GBS = 8000.0
-# algorithmic bytes per lattice update: Q loads + Q stores + one phi value
-BYTES_PER_LUP = {"fp64": 19 * 8 * 2 + 8, "fp32_shifted": 19 * 4 * 2 + 4,
-                 "fp16_shifted": 19 * 2 * 2 + 4}
+# algorithmic bytes per cell and launch: Q loads + Q stores + one phi value
+# (one lattice update per cell for the single-step kernel, two for the
+# two-step kernel)
+BYTES_PER_PASS = {"fp64": 19 * 8 * 2 + 8, "fp32_shifted": 19 * 4 * 2 + 4,
+                  "fp16_shifted": 19 * 2 * 2 + 4}
 DTYPE_NAME = {"fp64": "f64", "fp32_shifted": "f32", "fp16_shifted": "f32"}
-KERNEL_NAME = {"fp64": "step_kernel<D3Q19, FP64>",
-               "fp32_shifted": "step_kernel<D3Q19, FP32_SHIFTED>",
-               "fp16_shifted": "step_kernel<D3Q19, FP16_SHIFTED>"}
+MODE_NAME = {"fp64": "FP64", "fp32_shifted": "FP32_SHIFTED", "fp16_shifted": "FP16_SHIFTED"}
+
+
+def kernel_name(variant, two_step, lattice="D3Q19"):
+    return "%s<%s, %s>" % ("fused2_kernel" if two_step else "step_kernel", lattice,
+                           MODE_NAME[variant])
 
 
 def kernel_source_hash():
@@ -45,9 +52,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(variant):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+def measured_traffic(variant, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic_d3q19_256.json")
     if not os.path.exists(path):
         return None
@@ -56,16 +63,24 @@ def measured_traffic(variant):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     v = rec.get("variants", {}).get(variant)
-    return None if v is None else round(v.get("bytes_per_launch"))
+    if v is None or v.get("kernel") != kernel:
+        return None
+    return round(v.get("bytes_per_launch"))
 
 
 # launch shapes the autotuner picks for this workload on MI355X (used with
 # --fixed-launch, e.g. under a counter profiler that perturbs timing)
-FIXED_LAUNCH = {"fp32_shifted": (1024, 1, True), "fp64": (512, 1, True),
-                "fp16_shifted": (256, 4, False)}
+# (tile_x, tile_y, flat, two-step rows, two-step planes)
+FIXED_LAUNCH = {"fp32_shifted": (1024, 1, True, 4, 64), "fp64": (512, 1, True, 2, 64),
+                "fp16_shifted": (256, 4, False, 0, 0)}
+SINGLE_LAUNCH = {"fp32_shifted": (1024, 1, True, 0, 0), "fp64": (512, 1, True, 0, 0),
+                 "fp16_shifted": (256, 4, False, 0, 0)}
 
 
 def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
+    """Time `steps` steps of one storage variant.  fixed_launch: False =
+    autotuned shape; True = the recorded shape of FIXED_LAUNCH; a tuple =
+    that shape (tile_x, tile_y, flat, two-step rows, two-step planes)."""
     import torch
 
     from paper_2208_09267_amd import vanse
@@ -75,16 +90,28 @@ def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
     s.set_force(w.force)
     s.init(None, u0_t)
     if fixed_launch:
-        tile_x, tile_y, flat = FIXED_LAUNCH[variant]
+        shape = FIXED_LAUNCH[variant] if fixed_launch is True else fixed_launch
+        tile_x, tile_y, flat, rows, planes = shape
         flags = 4 if flat else 0
         s.set_tuning(tile_x, flags)
         s.set_tile(tile_x, tile_y)
+        s.set_fused(rows, planes)
+        fused = (rows, planes)
         ran = 0
     else:
         # warm-up: the autotuner's trial steps are real (untimed) steps
-        tile_x, tile_y, flags, ran = s.autotune(max(1, min(4, warmup // 6)))
-    s.step(max(0, warmup - ran))
+        L = s.autotune(max(1, min(4, warmup // 12)) * 2)
+        tile_x, tile_y, flags, ran = L.tile_x, L.tile_y, L.flags, L.steps_run
+        fused = (L.fused_rows, L.fused_planes)
+    two_step = fused[0] > 0
+    extra = max(0, warmup - ran)
+    if two_step and (s.time + extra) % 2:
+        extra += 1  # start the timed region at an even level: two-step launches only
+    s.step(extra)
+    if two_step and steps % 2:
+        steps += 1
     torch.cuda.synchronize()
+    # the events are recorded on torch's current stream, which the solver launches on
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -97,12 +124,21 @@ def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
     mass = s.diagnostics()[0]
     s.close()
     ms_step = ms / steps
+    per_launch = 2 if two_step else 1
+    launch_ms = ms_step * per_launch
     mlups = w.ncells * steps / (ms / 1e3) / 1e6
-    gbs = BYTES_PER_LUP[variant] * w.ncells / (ms_step / 1e3) / 1e9
-    launch = {"tile_x": tile_x, "tile_y": tile_y, "flat": bool(flags & 4)}
-    return {"mlups": mlups, "ms_per_step": ms_step, "wall_s": wall, "gb_s": gbs,
-            "frac_hbm": gbs / PEAK_HBM_GBS, "bytes_per_lup": BYTES_PER_LUP[variant],
-            "mass": mass, "launch": launch}
+    bytes_launch = BYTES_PER_PASS[variant] * w.ncells
+    gbs = bytes_launch / (launch_ms / 1e3) / 1e9
+    eff = BYTES_PER_PASS[variant] * mlups * 1e6 / 1e9
+    launch = {"tile_x": tile_x, "tile_y": tile_y, "flat": bool(flags & 4),
+              "two_step_rows": fused[0], "two_step_planes": fused[1]}
+    return {"mlups": mlups, "ms_per_step": ms_step, "ms_per_launch": launch_ms,
+            "steps_per_launch": per_launch, "wall_s": wall, "gb_s": gbs,
+            "frac_hbm": gbs / PEAK_HBM_GBS, "bytes_per_launch": bytes_launch,
+            "bytes_per_lup": BYTES_PER_PASS[variant] / per_launch,
+            "effective_gb_s": eff, "effective_frac": eff / PEAK_HBM_GBS,
+            "kernel": kernel_name(variant, two_step), "mass": mass, "launch": launch,
+            "steps": steps}
 
 
 def d3q27_run(steps=200, warmup=30):
@@ -126,8 +162,11 @@ def d3q27_run(steps=200, warmup=30):
         s = vanse.Solver("D3Q27", w.dims, w.tau, dt)
         s.set_porosity(w.eps_mean, pert, w.period)
         s.init(None, u0)
-        tx, ty, flags, ran = s.autotune(4)
-        s.step(max(0, warmup - ran))
+        L = s.autotune(4)
+        extra = max(0, warmup - L.steps_run)
+        if L.fused_rows and (s.time + extra) % 2:
+            extra += 1
+        s.step(extra)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -136,11 +175,17 @@ def d3q27_run(steps=200, warmup=30):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         s.close()
-        gbs = bpl * w.ncells / (ms / 1e3) / 1e9
+        per_launch = 2 if L.fused_rows else 1
+        gbs = bpl * w.ncells / (ms * per_launch / 1e3) / 1e9
         out[name] = {"mlups": round(w.ncells / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5),
-                     "bytes_per_lup": bpl, "gb_s": round(gbs, 1),
+                     "kernel": "%s<D3Q27, %s>" % ("fused2_kernel" if L.fused_rows else "step_kernel",
+                                                  "FP64" if dt == vanse.FP64 else "FP32_SHIFTED"),
+                     "bytes_per_lup": bpl / per_launch, "gb_s": round(gbs, 1),
                      "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
-                     "launch": {"tile_x": tx, "tile_y": ty, "flat": bool(flags & 4)}}
+                     "effective_frac_single_step_bytes":
+                         round(bpl * w.ncells / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                     "launch": {"tile_x": L.tile_x, "tile_y": L.tile_y, "flat": bool(L.flags & 4),
+                                "two_step_rows": L.fused_rows, "two_step_planes": L.fused_planes}}
     return out
 
 
@@ -179,7 +224,7 @@ def batched_run(steps=500, trial=5):
     b.close()
     for s in solvers:
         s.close()
-    gbs = BYTES_PER_LUP["fp32_shifted"] * cells * timed / (ms / 1e3) / 1e9
+    gbs = BYTES_PER_PASS["fp32_shifted"] * cells * timed / (ms / 1e3) / 1e9
     return {"workload": "64 D3Q19 solves, edges uniform in {32,48,64,96}, tau U[0.55,1.0], "
                         "seeded phi per solve, FP32 shifted, %d steps each" % steps,
             "total_cells": cells, "steps_timed": timed, "autotune_steps": run,
@@ -378,6 +423,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-d3q27", action="store_true")
+    ap.add_argument("--no-single-step", action="store_true",
+                    help="skip the single-step comparison run of two-step variants")
     ap.add_argument("--fixed-launch", action="store_true",
                     help="use the recorded launch shapes instead of autotuning")
     ap.add_argument("--precision", action="store_true",
@@ -423,13 +470,27 @@ def main():
     results = {}
     for v in variants:
         results[v] = gpu_variant(v, w, pert_t, u0_t, args.steps, args.warmup, args.fixed_launch)
-        print("# %s: %.1f MLUPS, %.4f ms/step, %.0f GB/s (%.1f%% of 8 TB/s)"
-              % (v, results[v]["mlups"], results[v]["ms_per_step"], results[v]["gb_s"],
-                 100 * results[v]["frac_hbm"]), file=sys.stderr, flush=True)
+        print("# %s: %.1f MLUPS, %.4f ms/step, %s %.0f GB/s (%.1f%% of 8 TB/s; "
+              "single-step equivalent %.1f%%)"
+              % (v, results[v]["mlups"], results[v]["ms_per_step"], results[v]["kernel"],
+                 results[v]["gb_s"], 100 * results[v]["frac_hbm"],
+                 100 * results[v]["effective_frac"]), file=sys.stderr, flush=True)
+    # the single-step kernel on the same workload, for comparison
+    single = {}
+    if not args.no_single_step:
+        for v in variants:
+            if results[v]["launch"]["two_step_rows"]:
+                x = gpu_variant(v, w, pert_t, u0_t, min(args.steps, 400), args.warmup,
+                                SINGLE_LAUNCH[v])
+                single[v] = {"mlups": round(x["mlups"], 1), "ms_per_step": round(x["ms_per_step"], 5),
+                             "gb_s": round(x["gb_s"], 1), "frac_hbm": round(x["frac_hbm"], 4),
+                             "kernel": x["kernel"], "steps": x["steps"]}
+                print("# %s single-step kernel: %.1f MLUPS" % (v, x["mlups"]), file=sys.stderr,
+                      flush=True)
 
     head = variants[0]
     r = results[head]
-    traffic = measured_traffic(head)
+    traffic = measured_traffic(head, r["kernel"])
     out = {
         "metric": METRIC,
         "value": round(r["mlups"], 1),
@@ -448,18 +509,27 @@ def main():
                                "amplitude 0.02",
                    "lattice": "D3Q19", "dims": list(w.dims), "tau": w.tau,
                    "storage": head, "global_batch": 1},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAME[head],
+        "roofline": {"bound": "hbm", "kernel": r["kernel"],
                      "achieved": round(r["gb_s"], 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(r["frac_hbm"], 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                      "calibrated on a copy kernel)",
-                     "algorithmic_bytes_per_launch": r["bytes_per_lup"] * w.ncells,
-                     "bytes_per_lup": r["bytes_per_lup"], "lups_per_launch": w.ncells},
+                     "algorithmic_bytes_per_launch": r["bytes_per_launch"],
+                     "ms_per_launch": round(r["ms_per_launch"], 5),
+                     "lups_per_launch": w.ncells * r["steps_per_launch"],
+                     "bytes_per_lup": r["bytes_per_lup"],
+                     "effective_gb_s_single_step_bytes": round(r["effective_gb_s"], 1),
+                     "effective_frac_single_step_bytes": round(r["effective_frac"], 4)},
         "variants": {v: {"mlups": round(x["mlups"], 1), "ms_per_step": round(x["ms_per_step"], 5),
+                         "kernel": x["kernel"], "ms_per_launch": round(x["ms_per_launch"], 5),
                          "gb_s": round(x["gb_s"], 1), "frac_hbm": round(x["frac_hbm"], 4),
-                         "bytes_per_lup": x["bytes_per_lup"], "launch": x["launch"]}
+                         "bytes_per_lup": x["bytes_per_lup"],
+                         "effective_frac_single_step_bytes": round(x["effective_frac"], 4),
+                         "launch": x["launch"]}
                      for v, x in results.items()},
     }
+    if single:
+        out["single_step_kernel"] = single
     if not args.no_copy_probe:
         out["copy_probe"] = copy_probe()
     if not args.no_d3q27:

@@ -169,9 +169,12 @@ typedef struct vanse_batch *vanse_batch_t;
 
 /* Create a batch over `count` >= 1 distinct, initialised solvers that share
  * lattice and dtype (host array of handles).  The batch does not own them:
- * they must outlive it and must not be stepped by vanse_step while it
- * exists.  Allocates small device tables (hipMalloc).  Errors: EINVAL,
- * ESTATE, ENOMEM, EDEVICE. */
+ * they must outlive it.  A member may also be stepped alone between batch
+ * calls, in stream order with the batch: the batch follows its time level
+ * and, after two-step launches, its current population array (the batch
+ * then rebuilds its tables once, synchronising its stream).  Allocates
+ * small device tables (hipMalloc).  Errors: EINVAL, ESTATE, ENOMEM,
+ * EDEVICE. */
 int vanse_batch_create(const vanse_t *solvers, int count, vanse_batch_t *out);
 
 /* Replace the members of b by `count` other (or the same) solvers of the
@@ -215,16 +218,48 @@ const char *vanse_batch_last_error(vanse_batch_t b);
  * Errors: EINVAL. */
 int vanse_set_tile(vanse_t h, int tile_x, int tile_y);
 
+/* Two-step launch of vanse_step (3-D lattices, temporal blocking): one
+ * launch advances two time levels.  It reads the populations at an even
+ * level n from the solver's array and writes level n + 2 into a second
+ * array of the same size (allocated here, so the population memory of the
+ * solve doubles), keeping level n + 1 in LDS: the populations cross HBM
+ * once per two lattice updates, plus the re-read halo of each tile.  A
+ * block owns `rows` full x-rows of `planes` consecutive z-planes and
+ * marches through them in z (halo: one x-row on each side and one plane at
+ * each end of the segment).  vanse_step takes every pair of steps that
+ * starts at an even level this way; a step left over (odd level, or odd n)
+ * uses the single-step kernel.  Results are bitwise identical to single
+ * steps.  Requires nx a multiple of 64, ny a multiple of rows, planes >= 1,
+ * and a tile shape compiled into the library (the shapes whose registers
+ * fit without spilling): with I = ceil(nx * rows / 512) interior and
+ * H = ceil(nx * (rows + 2) / 512) halo cells per thread,
+ *   D3Q19, FP32/FP16 storage: I <= 2 and H <= I + 2
+ *   D3Q19, FP64: I = 1 and H <= 2
+ *   D3Q27, FP32/FP16 storage: I = 1 and H <= 3, or I = 2 and H = 2
+ *   D3Q27, FP64: none (single steps only),
+ * and the block's LDS (Q * nx * rows stored populations plus 5 * (rows + 4)
+ * * nx perturbation values) within 160 KiB.
+ * rows = 0 switches the launch off and frees the second array.
+ * Synchronises the solver's stream when it allocates or frees.
+ * Errors: EINVAL, ENOMEM. */
+int vanse_set_fused(vanse_t h, int rows, int planes);
+
 /* Autotune the launch shape of vanse_step: each candidate (tiled 256-cell
  * row segments with 1, 2 or 4 rows per block where they divide the
- * lattice; flat launches of 256, 512 and 1024 threads) runs
- * `steps_per_trial` REAL steps timed with HIP events, and the fastest is
- * kept and cached for solves of the same lattice, dtype and size class.
+ * lattice; flat launches of 256, 512 and 1024 threads; on 3-D lattices the
+ * two-step launch of vanse_set_fused with 1, 2, 4 or 8 rows and 8, 32 or
+ * 64 planes where its shape exists) runs `steps_per_trial` REAL steps timed
+ * with HIP events, and the fastest is kept and cached for solves of the same
+ * lattice, dtype and size class.  *fused_rows / *fused_planes report the
+ * chosen two-step tile (0 / 0: single steps; the tile of the single-step
+ * kernel is still reported and used for leftover steps).  The two-step
+ * candidates need the second population array of vanse_set_fused: it is
+ * allocated for the trials and freed again unless a two-step launch wins.
  * The solve advances (number of candidates) * steps_per_trial steps, or 0
  * when the choice came from the cache (*steps_run tells).  Synchronises.
- * Errors: EINVAL, ESTATE, EDEVICE. */
+ * Any output pointer may be NULL.  Errors: EINVAL, ESTATE, ENOMEM, EDEVICE. */
 int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int *flags,
-                   int64_t *steps_run);
+                   int *fused_rows, int *fused_planes, int64_t *steps_run);
 
 /* Current time level n (number of steps since vanse_init). */
 int vanse_time(vanse_t h, int64_t *t);

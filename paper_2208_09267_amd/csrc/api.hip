@@ -24,6 +24,7 @@ struct vanse_solver {
 
 struct vanse_batch {
     std::vector<vanse_t> members;
+    std::vector<void *> layout_f;       // members' population arrays in the member table
     int lattice = 0, mode = 0, count = 0;
     int block = 256;
     bool nt = false;
@@ -86,6 +87,13 @@ StepArgs step_args(const Solver &s, int64_t n)
     a.fd_ny = make_fastdiv((unsigned)s.geo.ny);
     a.fd_seg = make_fastdiv(a.nseg);
     a.fd_nyb = make_fastdiv(a.nyb);
+    a.f2 = s.f_alt;
+    a.m2 = modulation(n + 1, s.period);
+    a.fty = (unsigned)std::max(s.fused_rows, 1);
+    a.fsz = (unsigned)std::max(s.fused_planes, 1);
+    a.fnyb = (unsigned)(s.geo.ny / (int)a.fty);
+    a.fd_fnyb = make_fastdiv(std::max(a.fnyb, 1u));
+    a.trash = s.scratch ? s.scratch + kTrashSlot : nullptr;
     return a;
 }
 
@@ -184,6 +192,7 @@ int vanse_destroy(vanse_t h)
     Solver &s = h->s;
     (void)hipStreamSynchronize(s.stream);
     (void)hipFree(s.f);
+    (void)hipFree(s.f_alt);
     (void)hipFree(s.pert);
     (void)hipFree(s.scratch);
     (void)hipFree(s.force);
@@ -325,11 +334,22 @@ int vanse_step(vanse_t h, int64_t n)
     if (n < 0) return fail(&s, VANSE_EINVAL, "vanse_step: n must be >= 0");
     if (!s.initialized) return fail(&s, VANSE_ESTATE, "vanse_step: call vanse_init first");
     if (s.unstable) return fail(&s, VANSE_EUNSTABLE, "vanse_step: solver is unstable");
-    for (int64_t k = 0; k < n; ++k) {
+    int64_t k = 0;
+    while (k < n) {
         const vanse::StepArgs a = vanse::step_args(s, s.t);
+        if (s.fused_rows > 0 && (s.t & 1) == 0 && n - k >= 2) {
+            // levels t -> t + 2 into the second array, which becomes current
+            hipError_t e = vanse::launch_fused(s, a);
+            if (e != hipSuccess) return hip_fail(&s, e, "vanse_step (two-step launch)");
+            std::swap(s.f, s.f_alt);
+            s.t += 2;
+            k += 2;
+            continue;
+        }
         hipError_t e = vanse::launch_step(s, a, (int)(s.t & 1));
         if (e != hipSuccess) return hip_fail(&s, e, "vanse_step");
         ++s.t;
+        ++k;
     }
     return VANSE_OK;
 }
@@ -408,18 +428,61 @@ int vanse_set_tile(vanse_t h, int tile_x, int tile_y)
     return VANSE_OK;
 }
 
+int vanse_set_fused(vanse_t h, int rows, int planes)
+{
+    if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_set_fused: NULL handle");
+    Solver &s = h->s;
+    hipError_t e;
+    if (rows == 0) {
+        if (s.f_alt) {
+            if ((e = hipStreamSynchronize(s.stream)) != hipSuccess)
+                return hip_fail(&s, e, "vanse_set_fused");
+            (void)hipFree(s.f_alt);
+            s.f_alt = nullptr;
+        }
+        s.fused_rows = s.fused_planes = 0;
+        return VANSE_OK;
+    }
+    if (s.d != 3) return fail(&s, VANSE_EINVAL, "vanse_set_fused: 3-D lattices only");
+    if (rows < 0 || planes < 1)
+        return fail(&s, VANSE_EINVAL, "vanse_set_fused: rows must be >= 0 and planes >= 1");
+    if (s.geo.ny % rows != 0)
+        return fail(&s, VANSE_EINVAL, "vanse_set_fused: rows must divide ny");
+    const size_t lds = vanse::fused_lds_bytes(s.q, s.mode, s.geo.nx, rows);
+    if (!vanse::fused_shape(s.lattice, s.mode, s.geo.nx, rows, nullptr, nullptr) ||
+        lds > (size_t)vanse::kFusedMaxLds)
+        return fail(&s, VANSE_EINVAL,
+                    "vanse_set_fused: no compiled tile of nx = " + std::to_string(s.geo.nx) +
+                        " x " + std::to_string(rows) +
+                        " rows for this lattice and dtype (nx must be a multiple of 64)");
+    if (!s.f_alt) {
+        if ((e = hipMalloc(&s.f_alt, s.f_bytes)) != hipSuccess) {
+            s.f_alt = nullptr;
+            (void)hipGetLastError();
+            return fail(&s, VANSE_ENOMEM,
+                        std::string("vanse_set_fused: hipMalloc failed: ") + hipGetErrorString(e));
+        }
+    }
+    s.fused_rows = rows;
+    s.fused_planes = planes;
+    return VANSE_OK;
+}
+
 }  // extern "C"
 
 namespace {
+struct SoloChoice {
+    int tile_x, tile_y, flat, fused_rows, fused_planes;
+};
 std::mutex g_solo_tune_mu;
-// (lattice, mode, log2 cells, nx % 256, ny % 4) -> (tile_x, tile_y, flat)
-std::map<std::tuple<int, int, int, int, int>, std::tuple<int, int, int>> g_solo_tune_cache;
+// (lattice, mode, log2 cells, nx, ny % 8) -> launch shape
+std::map<std::tuple<int, int, int, int, int>, SoloChoice> g_solo_tune_cache;
 }  // namespace
 
 extern "C" {
 
 int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int *flags,
-                   int64_t *steps_run)
+                   int *fused_rows, int *fused_planes, int64_t *steps_run)
 {
     if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_autotune: NULL handle");
     Solver &s = h->s;
@@ -427,36 +490,55 @@ int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int
     if (!s.initialized) return fail(&s, VANSE_ESTATE, "vanse_autotune: call vanse_init first");
     int cls = 0;
     while ((int64_t(1) << (cls + 1)) <= (int64_t)s.geo.ncells) ++cls;
-    const auto key = std::make_tuple(s.lattice, s.mode, cls, s.geo.nx % 256, s.geo.ny % 4);
-    int bx = 256, by = 1, flat = 0;
+    const auto key = std::make_tuple(s.lattice, s.mode, cls, s.geo.nx, s.geo.ny % 8);
+    SoloChoice best_c{256, 1, 0, 0, 0};
     int64_t run = 0;
     bool cached = false;
     {
         std::lock_guard<std::mutex> lk(g_solo_tune_mu);
         auto it = g_solo_tune_cache.find(key);
         if (it != g_solo_tune_cache.end()) {
-            std::tie(bx, by, flat) = it->second;
+            best_c = it->second;
             cached = true;
         }
     }
     const int keep_flags = s.flags & ~VANSE_TUNE_FLAT;
     if (!cached) {
-        // candidates: tiled x-row segments of 256 cells with 1, 2, 4 rows, and the
-        // flattened launch with 256, 512, 1024 threads
-        const int cand[6][3] = {{256, 1, 0}, {256, 2, 0}, {256, 4, 0},
-                                {256, 1, 1}, {512, 1, 1}, {1024, 1, 1}};
+        // single-step candidates: tiled x-row segments of 256 cells with 1, 2, 4
+        // rows, and the flattened launch with 256, 512, 1024 threads; then the
+        // two-step launch with 1, 2, 4, 8 rows and 8, 32 or 64 planes
+        std::vector<SoloChoice> cand = {{256, 1, 0, 0, 0}, {256, 2, 0, 0, 0}, {256, 4, 0, 0, 0},
+                                        {256, 1, 1, 0, 0}, {512, 1, 1, 0, 0}, {1024, 1, 1, 0, 0}};
+        if (s.d == 3) {
+            const int rows[4] = {1, 2, 4, 8};
+            const int planes[3] = {8, 32, 64};
+            for (int r : rows)
+                for (int p : planes) {
+                    const size_t lds = vanse::fused_lds_bytes(s.q, s.mode, s.geo.nx, r);
+                    if (s.geo.ny % r == 0 && lds <= (size_t)vanse::kFusedMaxLds &&
+                        vanse::fused_shape(s.lattice, s.mode, s.geo.nx, r, nullptr, nullptr))
+                        cand.push_back({256, 1, 1, r, p});
+                }
+        }
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
             return fail(&s, VANSE_EDEVICE, "vanse_autotune: event creation failed");
-        float best = 1e30f;
+        float best = 1e30f, best_single = 1e30f;
+        SoloChoice single_c = best_c;
         int rc = VANSE_OK;
-        for (int c = 0; c < 6 && rc == VANSE_OK; ++c) {
-            const bool tiled_ok = s.geo.nx % cand[c][0] == 0 && s.geo.ny % cand[c][1] == 0;
-            if (!cand[c][2] && !tiled_ok) continue;  // would fall back to a flat launch
-            if (cand[c][0] * cand[c][1] > max_threads(s)) continue;
-            s.tile_x = cand[c][0];
-            s.tile_y = cand[c][1];
-            s.allow_row = !cand[c][2];
+        for (const SoloChoice &c : cand) {
+            if (rc != VANSE_OK) break;
+            const bool tiled_ok = s.geo.nx % c.tile_x == 0 && s.geo.ny % c.tile_y == 0;
+            if (!c.flat && !tiled_ok) continue;  // would fall back to a flat launch
+            if (c.tile_x * c.tile_y > max_threads(s)) continue;
+            if (c.fused_rows) {
+                if (vanse_set_fused(h, c.fused_rows, c.fused_planes) != VANSE_OK) continue;
+            } else if (s.fused_rows) {
+                s.fused_rows = s.fused_planes = 0;  // keep the second array for later trials
+            }
+            s.tile_x = c.tile_x;
+            s.tile_y = c.tile_y;
+            s.allow_row = !c.flat;
             (void)hipEventRecord(e0, s.stream);
             rc = vanse_step(h, steps_per_trial);
             (void)hipEventRecord(e1, s.stream);
@@ -466,24 +548,34 @@ int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int
             run += steps_per_trial;
             if (rc == VANSE_OK && ms < best) {
                 best = ms;
-                bx = cand[c][0];
-                by = cand[c][1];
-                flat = cand[c][2];
+                best_c = c;
+            }
+            if (rc == VANSE_OK && !c.fused_rows && ms < best_single) {
+                best_single = ms;
+                single_c = c;
             }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc != VANSE_OK) return rc;
+        // a leftover single step of the two-step choice uses the best single-step shape
+        best_c.tile_x = single_c.tile_x;
+        best_c.tile_y = single_c.tile_y;
+        best_c.flat = single_c.flat;
         std::lock_guard<std::mutex> lk(g_solo_tune_mu);
-        g_solo_tune_cache[key] = std::make_tuple(bx, by, flat);
+        g_solo_tune_cache[key] = best_c;
     }
-    s.tile_x = bx;
-    s.tile_y = by;
-    s.allow_row = !flat;
+    s.tile_x = best_c.tile_x;
+    s.tile_y = best_c.tile_y;
+    s.allow_row = !best_c.flat;
     s.flags = keep_flags;
-    if (tile_x) *tile_x = bx;
-    if (tile_y) *tile_y = by;
-    if (flags) *flags = keep_flags | (flat ? VANSE_TUNE_FLAT : 0);
+    int rc = vanse_set_fused(h, best_c.fused_rows, best_c.fused_planes);
+    if (rc != VANSE_OK) return rc;
+    if (tile_x) *tile_x = best_c.tile_x;
+    if (tile_y) *tile_y = best_c.tile_y;
+    if (flags) *flags = keep_flags | (best_c.flat ? VANSE_TUNE_FLAT : 0);
+    if (fused_rows) *fused_rows = best_c.fused_rows;
+    if (fused_planes) *fused_planes = best_c.fused_planes;
     if (steps_run) *steps_run = run;
     return VANSE_OK;
 }
@@ -499,7 +591,8 @@ int vanse_device_bytes(vanse_t h, int64_t *bytes)
 {
     if (!h || !bytes)
         return fail(h ? &h->s : nullptr, VANSE_EINVAL, "vanse_device_bytes: NULL argument");
-    *bytes = (int64_t)(h->s.f_bytes + h->s.pert_bytes + h->s.scratch_bytes + h->s.force_bytes);
+    *bytes = (int64_t)(h->s.f_bytes * (h->s.f_alt ? 2 : 1) + h->s.pert_bytes +
+                       h->s.scratch_bytes + h->s.force_bytes);
     return VANSE_OK;
 }
 
@@ -609,8 +702,10 @@ int batch_layout(vanse_batch *b)
     std::vector<vanse::BatchMember> mem(b->count);
     std::vector<unsigned> owner;
     unsigned begin = 0;
+    b->layout_f.assign(b->count, nullptr);
     for (int k = 0; k < b->count; ++k) {
         const Solver &s = b->members[k]->s;
+        b->layout_f[k] = s.f;
         vanse::BatchMember &m = mem[k];
         m.a = vanse::step_args(s, s.t);
         m.a.block = (unsigned)b->block;
@@ -707,8 +802,18 @@ int batch_capture(vanse_batch *b)
 
 int batch_run(vanse_batch *b, int64_t n, bool allow_graph)
 {
-    for (auto *h : b->members)
-        if (h->s.unstable) return bfail(b, VANSE_EUNSTABLE, "vanse_batch_step: a member is unstable");
+    bool moved = false;
+    for (int k = 0; k < b->count; ++k) {
+        const Solver &s = b->members[k]->s;
+        if (s.unstable) return bfail(b, VANSE_EUNSTABLE, "vanse_batch_step: a member is unstable");
+        moved = moved || s.f != b->layout_f[k];
+    }
+    if (moved) {  // a member switched population arrays (two-step launch) since the layout
+        hipError_t e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bfail(b, VANSE_EDEVICE, std::string("vanse_batch_step: ") + hipGetErrorString(e));
+        int rc = batch_layout(b);
+        if (rc != VANSE_OK) return rc;
+    }
     while (n > 0) {
         const int k = (int)std::min<int64_t>(n, b->chunk_cap);
         int rc = batch_upload(b, k);

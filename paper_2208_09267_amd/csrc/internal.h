@@ -60,6 +60,14 @@ struct StepArgs {
     unsigned nseg;       // tiled: segments per x-row (nx / tx)
     unsigned nyb;        // tiled: row blocks per z-plane (ny / ty)
     FastDiv fd_nx, fd_ny, fd_seg, fd_nyb;
+    // two-step launch (fused2_kernel): n -> n + 2 from f into f2
+    void *f2;            // destination populations (natural order at n + 2)
+    double m2;           // modulation m(n + 1) of the second step
+    unsigned fty;        // full x-rows per tile
+    unsigned fsz;        // z-planes per tile segment
+    unsigned fnyb;       // tiles per z-segment (ny / fty)
+    FastDiv fd_fnyb;
+    void *trash;         // 8-byte device slot for discarded stores
 };
 
 // One solve inside a batched launch (device-resident table).
@@ -82,8 +90,11 @@ struct Solver {
     int tile_y = 1;              //   and rows per block
     int flags = 0;               // step-kernel variant flags (StepArgs::flags)
     bool allow_row = true;       // use the tiled launch when the tile divides the lattice
-    void *f = nullptr;           // populations
+    void *f = nullptr;           // populations (current time level)
     size_t f_bytes = 0;
+    int fused_rows = 0;          // two-step launch: x-rows per tile (0 = off)
+    int fused_planes = 0;        //   and z-planes per segment
+    void *f_alt = nullptr;       // second population array of the two-step launch
     void *pert = nullptr;        // phi perturbation (double or float)
     size_t pert_bytes = 0;
     void *force = nullptr;       // per-cell force density (double or float), optional
@@ -97,12 +108,35 @@ struct Solver {
 
 constexpr int kReduceBlocks = 1024;   // fixed grid of the reduction kernels
 constexpr int kReduceThreads = 256;
+// scratch (doubles): reduction partials [7 * kReduceBlocks], results [7], and
+// from kTrashSlot on a slot that discarded kernel stores may write
+constexpr int kTrashSlot = 7 * kReduceBlocks + 32;
 
 double modulation(int64_t n, double period);
 StepArgs step_args(const Solver &s, int64_t n);
 
 // Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_step(const Solver &s, const StepArgs &a, int parity);
+constexpr int kFusedThreads = 512;    // threads per block of the two-step launch
+constexpr int kFusedMaxLds = 160 * 1024;
+// Tile shapes of the two-step launch compiled into the library: ipt interior
+// and hpt halo-plane cells per thread, kept to the combinations whose
+// registers fit without spilling on gfx950.
+constexpr bool fused_compiled(int lattice, int mode, int ipt, int hpt)
+{
+    if (lattice == 0 || ipt < 1 || hpt < ipt) return false;
+    if (lattice == 2)  // D3Q27: 27 populations per cell in registers
+        return mode != MODE_F64 && (ipt == 1 ? hpt <= 3 : hpt <= 2);
+    if (mode == MODE_F64) return ipt == 1 && hpt <= 2;
+    return ipt <= 2 && hpt <= ipt + 2;
+}
+// Per-thread work counts of the two-step launch for a tile of `rows` full
+// x-rows; false if the lattice has no such compiled shape.
+bool fused_shape(int lattice, int mode, int nx, int rows, int *ipt, int *hpt);
+// LDS of one block of the two-step launch: the population slab and the ring
+// of 5 perturbation planes of rows + 4 x-rows.
+size_t fused_lds_bytes(int q, int mode, int nx, int rows);
+hipError_t launch_fused(const Solver &s, const StepArgs &a);
 hipError_t launch_init(const Solver &s, const double *rho0, const double *u0);
 hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, unsigned block,
                              const BatchMember *members, const unsigned *owner,

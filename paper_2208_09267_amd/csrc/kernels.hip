@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 #include <utility>
 
@@ -149,6 +150,14 @@ __device__ __forceinline__ Cell locate(const Geometry &g, int c)
     k.Z[1] = z * g.nxy;
     k.Z[2] = ((z + 1 == g.nz) ? 0 : z + 1) * g.nxy;
     return k;
+}
+
+// phi(x, t_n) = eps_mean + m(n) pert(x).  Every step kernel evaluates it
+// through this one expression, so all launch forms round it alike.
+template <class R>
+__device__ __forceinline__ R phi_of(R eps_mean, R m, R pert)
+{
+    return eps_mean + m * pert;
 }
 
 // Volume-fraction operators at one cell, at the current time level:
@@ -319,15 +328,15 @@ __device__ __forceinline__ void cell_step(const StepArgs &a, int x, int y, int z
     const R *__restrict__ pert = static_cast<const R *>(a.pert);
     const R em = R(a.eps_mean), mm = R(a.m);
     R e[7];
-    e[0] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[1] * sizeof(R));
-    e[1] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[2] * sizeof(R));
-    e[2] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[0] * sizeof(R));
-    e[3] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[2]), (unsigned)X[1] * sizeof(R));
-    e[4] = em + mm * ld<R, false>(pert + (Zo[1] + Yo[0]), (unsigned)X[1] * sizeof(R));
+    e[0] = phi_of(em, mm, ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[1] * sizeof(R)));
+    e[1] = phi_of(em, mm, ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[2] * sizeof(R)));
+    e[2] = phi_of(em, mm, ld<R, false>(pert + (Zo[1] + Yo[1]), (unsigned)X[0] * sizeof(R)));
+    e[3] = phi_of(em, mm, ld<R, false>(pert + (Zo[1] + Yo[2]), (unsigned)X[1] * sizeof(R)));
+    e[4] = phi_of(em, mm, ld<R, false>(pert + (Zo[1] + Yo[0]), (unsigned)X[1] * sizeof(R)));
     e[5] = e[6] = R(0);
     if constexpr (L::D == 3) {
-        e[5] = em + mm * ld<R, false>(pert + (Zo[2] + Yo[1]), (unsigned)X[1] * sizeof(R));
-        e[6] = em + mm * ld<R, false>(pert + (Zo[0] + Yo[1]), (unsigned)X[1] * sizeof(R));
+        e[5] = phi_of(em, mm, ld<R, false>(pert + (Zo[2] + Yo[1]), (unsigned)X[1] * sizeof(R)));
+        e[6] = phi_of(em, mm, ld<R, false>(pert + (Zo[0] + Yo[1]), (unsigned)X[1] * sizeof(R)));
     }
     R I, gx, gy, gz;
     eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
@@ -420,6 +429,235 @@ __global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__re
         cell_step<L, MODE, 1, NT ? 1 : 0>(a, x, y, z);
     else
         cell_step<L, MODE, 0, NT ? 1 : 0>(a, x, y, z);
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps in one launch (temporal blocking), 3-D lattices.
+//
+// Input: f at an even time level n in natural order (a.f).  Output: f at
+// n + 2 in natural order in a second array (a.f2).  A block owns the interior
+// tile of fty full x-rows (y0 .. y0+fty-1) of the z-planes z0 .. z1-1 and
+// marches in z over the planes p = z0-1 .. z1:
+//   1. step n on the fty + 2 rows y0-1 .. y0+fty of plane p (the two outer
+//      rows are recomputed by the neighbouring tiles too): natural loads, the
+//      phi stencil at m(n), collision -- the arithmetic of the even AA step;
+//   2. each post-collision value f*_i(x) is pushed into an LDS slab at its
+//      destination x + xi_i (slab [Q][nx * fty], indexed by direction and
+//      destination cell of the tile; values leaving the tile rows are
+//      dropped: the neighbouring tile computes them);
+//   3. each interior cell reads back the values streaming into it; those with
+//      xi_z = -1 complete plane p - 1, those with xi_z = 0 and +1 wait in
+//      registers for planes p and p + 1;
+//   4. step n + 1 on interior plane p - 1 (phi stencil at m(n+1)), results
+//      pushed to x + xi_i of a.f2.
+// The perturbation pert (phi = eps_mean + m pert) of the rows y0-2 ..
+// y0+fty+1 is staged in an LDS ring of 5 planes (p-2 .. p+2), so the cell
+// updates read no global memory.  The populations of plane p + 1 and the
+// pert rows of plane p + 3 are loaded before step 4 of plane p: they are in
+// flight while the block computes, and no later global load waits behind
+// them.  nx is a multiple of 64, so every wave lies in one x-row: row bases
+// are scalar and a lane carries one 32-bit offset.  Per launch every
+// population is loaded (fty + 2)/fty (fsz + 2)/fsz times and stored once for
+// two lattice updates.  The cell arithmetic is the one of cell_step (phi_of,
+// eps_combine, collide) and the intermediate values pass through the storage
+// encoding as they would through HBM, so one launch is bitwise equal to two
+// single steps.
+template <class L, int MODE, int IPT, int HPT>
+__global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
+{
+    static_assert(L::D == 3, "two-step launch: 3-D lattices only");
+    using St = Storage<MODE>;
+    using T = typename St::T;
+    using R = typename St::R;
+    constexpr int Q = L::Q;
+    constexpr int RING = 5;                 // pert planes p-2 .. p+2
+    constexpr int PPT = (5 * HPT + 2) / 3;  // pert values per thread and plane
+    extern __shared__ __align__(16) unsigned char fused_lds[];
+
+    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz, nxy = a.geo.nxy;
+    const long long S = a.geo.stride;
+    const int TY = (int)a.fty;
+    const int NI = nx * TY;          // interior cells of one plane of the tile
+    const int HC = NI + 2 * nx;      // cells of one plane with the two outer rows
+    const int PR = TY + 4;           // pert rows per plane: y0-2 .. y0+TY+1
+    const int PC = PR * nx;
+    T *__restrict__ slab = reinterpret_cast<T *>(fused_lds);
+    R *__restrict__ ring =
+        reinterpret_cast<R *>(fused_lds + ((size_t)Q * NI * sizeof(T) + 15) / 16 * 16);
+    const unsigned bz = fdiv(blockIdx.x, a.fd_fnyb);
+    const int y0 = (int)(blockIdx.x - bz * a.fnyb) * TY;
+    const int z0 = (int)bz * (int)a.fsz;
+    const int z1 = min(z0 + (int)a.fsz, nz);
+    const T *__restrict__ src = static_cast<const T *>(a.f);
+    T *__restrict__ dst = static_cast<T *>(a.f2);
+    const R *__restrict__ pert = static_cast<const R *>(a.pert);
+    const R *__restrict__ fc = static_cast<const R *>(a.force);
+    const R em = R(a.eps_mean);
+    const int tid = threadIdx.x;
+
+    // periodic index for v in [-n, 2n): neighbours and the halo of one tile
+    auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+    // periodic plane index for any v >= -3 (the prologue and the prefetch
+    // reach 2 planes below and 3 above the segment, also when nz < 3)
+    auto zmod = [&](int v) { return (v + 3 * nz) % nz; };
+    // wave-uniform x-row of a cell index of the tile (waves never straddle rows)
+    auto row_of = [&](int idx) {
+        return (int)__builtin_amdgcn_readfirstlane(fdiv((unsigned)idx, a.fd_nx));
+    };
+    // ring slot of plane q (q >= z0 - 2)
+    auto slot = [&](int q) { return (q - (z0 - 2)) % RING; };
+    // pert of tile row r (= y - y0 + 2) of plane q, from the ring
+    auto pring = [&](int q, int r, int x) { return ring[(slot(q) * PR + r) * nx + x]; };
+    // phi stencil, external + per-cell force and collision of one cell at
+    // (x, y, z) (y, z wave-uniform; r = y - y0 + 2 its ring row, q its plane
+    // index before wrapping) on the decoded values v, at modulation mm
+    auto update = [&](R (&v)[Q], int x, int y, int r, int q, int z, R mm) {
+        const int xm = (x == 0 ? nx : x) - 1, xp = (x + 1 == nx) ? 0 : x + 1;
+        R e[7];
+        e[0] = phi_of(em, mm, pring(q, r, x));
+        e[1] = phi_of(em, mm, pring(q, r, xp));
+        e[2] = phi_of(em, mm, pring(q, r, xm));
+        e[3] = phi_of(em, mm, pring(q, r + 1, x));
+        e[4] = phi_of(em, mm, pring(q, r - 1, x));
+        e[5] = phi_of(em, mm, pring(q + 1, r, x));
+        e[6] = phi_of(em, mm, pring(q - 1, r, x));
+        R I, gx, gy, gz;
+        eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
+        R Fex = R(a.F[0]), Fey = R(a.F[1]), Fez = R(a.F[2]);
+        if (fc) {
+            const R *row = fc + (z * nxy + y * nx);
+            const unsigned ox = (unsigned)x * (unsigned)sizeof(R);
+            Fex = Fex + ld<R, false>(row, ox);
+            Fey = Fey + ld<R, false>(row + S, ox);
+            Fez = Fez + ld<R, false>(row + 2 * S, ox);
+        }
+        collide<L, MODE, R>(v, I, gx, gy, gz, R(a.omega), R(a.fcoef), Fex, Fey, Fez);
+    };
+    // natural-order populations of the fty + 2 rows of plane p
+    auto load_plane = [&](T (&raw)[HPT][Q], int p) {
+        const int pz = zmod(p);
+        static_for<0, HPT>([&](auto hc) {
+            constexpr int h = decltype(hc)::value;
+            const int idx = min(tid + h * kFusedThreads, HC - 1);
+            const int hr = row_of(idx);
+            const int x = idx - hr * nx;
+            const int y = wrap(y0 + hr - 1, ny);
+            const T *base = src + (pz * nxy + y * nx);
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                raw[h][i] = ld<T, false>(base + i * S, (unsigned)x * (unsigned)sizeof(T));
+            });
+        });
+    };
+    // pert of the PR ring rows of plane q: into registers, then into the ring
+    auto load_pert = [&](R (&ph)[PPT], int q) {
+        const int qz = zmod(q);
+        static_for<0, PPT>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const int idx = min(tid + j * kFusedThreads, PC - 1);
+            const int r = row_of(idx);
+            const int x = idx - r * nx;
+            const int y = ((y0 + r - 2) % ny + ny) % ny;
+            ph[j] = ld<R, false>(pert + (qz * nxy + y * nx), (unsigned)x * (unsigned)sizeof(R));
+        });
+    };
+    auto store_pert = [&](const R (&ph)[PPT], int q) {
+        static_for<0, PPT>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            const int idx = min(tid + j * kFusedThreads, PC - 1);
+            ring[slot(q) * PC + idx] = ph[j];  // repeats write the same value
+        });
+    };
+
+    // Every iteration issues the same memory operations in the same order
+    // (pert loads, population loads, Q * IPT stores), so the hardware wait
+    // counts stay exact across the loop: threads past the end of the tile
+    // repeat its last cell, and stores that must not land (those repeats, and
+    // the two leading iterations that complete no plane) go to a trash slot.
+    R up_prev[IPT][Q] = {};  // xi_z = +1 values for plane p - 1 (read at p - 2)
+    R up_next[IPT][Q] = {};  // xi_z = +1 values for plane p (read at p - 1)
+    R mid[IPT][Q] = {};      // xi_z = 0 values for plane p - 1 (read at p - 1)
+    T raw[HPT][Q] = {};
+    R ph[PPT] = {};
+    T *__restrict__ trash = static_cast<T *>(a.trash);
+    for (int q = z0 - 2; q <= z0; ++q) {
+        load_pert(ph, q);
+        store_pert(ph, q);
+    }
+    load_pert(ph, z0 + 1);
+    load_plane(raw, z0 - 1);
+    static_for<0, IPT * Q>([&](auto) { st<T, false>(trash, 0u, T(0)); });
+
+    for (int p = z0 - 1; p <= z1; ++p) {
+        const int pz = wrap(p, nz);
+        __syncthreads();  // the slab and the ring slot of plane p - 3 are free
+        store_pert(ph, p + 2);
+        static_for<0, HPT>([&](auto hc) {
+            constexpr int h = decltype(hc)::value;
+            const int idx = min(tid + h * kFusedThreads, HC - 1);
+            const int hr = row_of(idx);
+            const int x = idx - hr * nx;
+            R v[Q];
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                v[i] = St::decode(raw[h][i]);
+            });
+            update(v, x, wrap(y0 + hr - 1, ny), hr + 1, p, pz, R(a.m));
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const int r = hr - 1 + L::cy[i];
+                if ((unsigned)r < (unsigned)TY) {  // wave-uniform
+                    const int xd = wrap(x + L::cx[i], nx);
+                    slab[i * NI + r * nx + xd] = St::encode(v[i]);
+                }
+            });
+        });
+        __syncthreads();  // slab of plane p and ring plane p + 2 complete
+        load_pert(ph, p + 3);
+        load_plane(raw, p + 1);
+        // interior plane p - 1 is completed from p = z0 + 1 on; before that the
+        // work is done on plane z0 (in range) and its results are discarded
+        const int z = max(p - 1, z0);
+        static_for<0, IPT>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            const bool own = tid + k * kFusedThreads < NI && p > z0;  // wave-uniform
+            const int cell = min(tid + k * kFusedThreads, NI - 1);
+            R t[Q];
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                t[i] = St::decode(slab[i * NI + cell]);
+            });
+            const int r = row_of(cell);
+            const int x = cell - r * nx;
+            const int y = y0 + r;
+            R w[Q];
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (L::cz[i] == 1) w[i] = up_prev[k][i];
+                else if constexpr (L::cz[i] == 0) w[i] = mid[k][i];
+                else w[i] = t[i];
+            });
+            update(w, x, y, r + 2, z, z, R(a.m2));
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const int yd = wrap(y + L::cy[i], ny);
+                const int zd = wrap(z + L::cz[i], nz);
+                const int xd = wrap(x + L::cx[i], nx);
+                T *base = own ? dst + i * S + (zd * nxy + yd * nx) : trash;
+                st<T, false>(base, own ? (unsigned)xd * (unsigned)sizeof(T) : 0u,
+                             St::encode(w[i]));
+            });
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if constexpr (L::cz[i] == 1) {
+                    up_prev[k][i] = up_next[k][i];
+                    up_next[k][i] = t[i];
+                } else if constexpr (L::cz[i] == 0) {
+                    mid[k][i] = t[i];
+                }
+            });
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -700,6 +938,82 @@ hipError_t launch_step(const Solver &s, const StepArgs &a, int parity)
             by_nt(std::false_type{});
         return hipGetLastError();
     });
+}
+
+size_t fused_lds_bytes(int q, int mode, int nx, int rows)
+{
+    const size_t elem = mode == MODE_F64 ? 8 : (mode == MODE_F32S ? 4 : 2);
+    const size_t slab = ((size_t)q * nx * rows * elem + 15) / 16 * 16;
+    const size_t ring = (size_t)5 * (rows + 4) * nx * (mode == MODE_F64 ? 8 : 4);
+    return slab + ring;
+}
+
+bool fused_shape(int lattice, int mode, int nx, int rows, int *ipt, int *hpt)
+{
+    if (nx < 64 || nx % 64 != 0 || rows < 1) return false;  // waves must not straddle x-rows
+    const long long ni = (long long)nx * rows, hc = ni + 2ll * nx;
+    const long long i = (ni + kFusedThreads - 1) / kFusedThreads;
+    const long long h = (hc + kFusedThreads - 1) / kFusedThreads;
+    if (i > 4 || h > 8) return false;
+    if (ipt) *ipt = (int)i;
+    if (hpt) *hpt = (int)h;
+    return fused_compiled(lattice, mode, (int)i, (int)h);
+}
+
+hipError_t launch_fused(const Solver &s, const StepArgs &a)
+{
+    int ipt = 0, hpt = 0;
+    if (!fused_shape(s.lattice, s.mode, a.geo.nx, (int)a.fty, &ipt, &hpt))
+        return hipErrorInvalidValue;
+    const size_t lds = fused_lds_bytes(s.q, s.mode, a.geo.nx, (int)a.fty);
+    if (lds > (size_t)kFusedMaxLds) return hipErrorInvalidValue;
+    const unsigned nzb = (unsigned)((a.geo.nz + (int)a.fsz - 1) / (int)a.fsz);
+    const unsigned nblocks = a.fnyb * nzb;
+    hipError_t rc = hipErrorInvalidValue;
+    auto go = [&](auto lat, auto mode, auto ic, auto hc) {
+        using L = decltype(lat);
+        constexpr int M = decltype(mode)::value;
+        constexpr int I = decltype(ic)::value;
+        constexpr int H = decltype(hc)::value;
+        constexpr int LAT = std::is_same<L, D3Q19>::value ? 1 : 2;
+        if constexpr (fused_compiled(LAT, M, I, H)) {
+            if (I != ipt || H != hpt) return;
+            auto *fn = &fused2_kernel<L, M, I, H>;
+            // slabs above 64 KiB need the kernel's LDS limit raised, once per device
+            static std::atomic<unsigned long long> raised{0};
+            int dev = 0;
+            if ((rc = hipGetDevice(&dev)) != hipSuccess) return;
+            const unsigned long long bit = 1ull << (dev & 63);
+            if (lds > 65536 && !(raised.load() & bit)) {
+                rc = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, kFusedMaxLds);
+                if (rc != hipSuccess) return;
+                raised.fetch_or(bit);
+            }
+            fn<<<nblocks, kFusedThreads, lds, s.stream>>>(a);
+            rc = hipGetLastError();
+        }
+    };
+    auto shapes = [&](auto lat, auto mode) {
+        using C1 = std::integral_constant<int, 1>;
+        using C2 = std::integral_constant<int, 2>;
+        using C3 = std::integral_constant<int, 3>;
+        using C4 = std::integral_constant<int, 4>;
+        go(lat, mode, C1{}, C1{});
+        go(lat, mode, C1{}, C2{});
+        go(lat, mode, C1{}, C3{});
+        go(lat, mode, C2{}, C2{});
+        go(lat, mode, C2{}, C3{});
+        go(lat, mode, C2{}, C4{});
+    };
+    auto modes = [&](auto lat) {
+        if (s.mode == MODE_F64) shapes(lat, std::integral_constant<int, MODE_F64>{});
+        else if (s.mode == MODE_F32S) shapes(lat, std::integral_constant<int, MODE_F32S>{});
+        else shapes(lat, std::integral_constant<int, MODE_F16S>{});
+    };
+    if (s.lattice == 1) modes(D3Q19{});
+    else modes(D3Q27{});
+    return rc;
 }
 
 hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, unsigned block,

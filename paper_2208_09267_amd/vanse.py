@@ -11,6 +11,7 @@ Low-level names mirror the C ABI (``vanse_create``, ``vanse_set_porosity``,
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import os
 import threading
@@ -35,12 +36,17 @@ EXPORTS = [
     "vanse_set_force", "vanse_init", "vanse_step", "vanse_moments", "vanse_diagnostics",
     "vanse_populations", "vanse_time", "vanse_device_bytes", "vanse_last_error",
     "vanse_lattice_info", "vanse_copy_probe", "vanse_set_tuning", "vanse_set_tile",
-    "vanse_autotune", "vanse_set_force_field",
+    "vanse_autotune", "vanse_set_force_field", "vanse_set_fused",
     "vanse_batch_create", "vanse_batch_destroy", "vanse_batch_set_stream",
     "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
     "vanse_batch_last_error", "vanse_batch_update",
 ]
 TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT, TUNE_NT_STORES = 1, 2, 4, 8
+
+
+class Launch(collections.namedtuple(
+        "Launch", "tile_x tile_y flags fused_rows fused_planes steps_run")):
+    """Launch shape chosen by Solver.autotune (fused_rows = 0: single steps)."""
 
 
 class VanseError(RuntimeError):
@@ -86,8 +92,10 @@ def load_library(path: str = LIB_PATH):
             "vanse_set_tuning": (i, [P, i, i]),
             "vanse_set_tile": (i, [P, i, i]),
             "vanse_set_force_field": (i, [P, P]),
+            "vanse_set_fused": (i, [P, i, i]),
             "vanse_autotune": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i),
-                                   ctypes.POINTER(i), I64P]),
+                                   ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i),
+                                   I64P]),
             "vanse_batch_create": (i, [ctypes.POINTER(P), i, ctypes.POINTER(P)]),
             "vanse_batch_destroy": (i, [P]),
             "vanse_batch_set_stream": (i, [P, P]),
@@ -212,14 +220,23 @@ class Solver:
         """Tile of the step kernel (see vanse_set_tile); bitwise-neutral."""
         self._check(self.lib.vanse_set_tile(self.h, int(tile_x), int(tile_y)))
 
+    def set_fused(self, rows=2, planes=32):
+        """Two-step launch with tiles of `rows` full x-rows and `planes`
+        z-planes (see vanse_set_fused; rows=0 switches it off); results are
+        bitwise identical to single steps."""
+        self._bind_stream()
+        self._check(self.lib.vanse_set_fused(self.h, int(rows), int(planes)))
+
     def autotune(self, steps_per_trial=4):
         """Pick the fastest launch shape on real steps (see vanse_autotune).
-        Returns (tile_x, tile_y, flags, steps_run)."""
+        Returns a Launch(tile_x, tile_y, flags, fused_rows, fused_planes,
+        steps_run)."""
         self._bind_stream()
-        bx, by, fl, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
-        self._check(self.lib.vanse_autotune(self.h, int(steps_per_trial), ctypes.byref(bx),
-                                            ctypes.byref(by), ctypes.byref(fl), ctypes.byref(n)))
-        return bx.value, by.value, fl.value, n.value
+        v = [ctypes.c_int() for _ in range(5)]
+        n = ctypes.c_int64()
+        self._check(self.lib.vanse_autotune(self.h, int(steps_per_trial),
+                                            *[ctypes.byref(x) for x in v], ctypes.byref(n)))
+        return Launch(*[x.value for x in v], n.value)
 
     def set_force_field(self, F=None):
         """Per-cell force density, FP64 [d, ncells] (None switches it off)."""

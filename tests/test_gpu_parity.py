@@ -221,13 +221,14 @@ def test_autotune_is_bitwise_neutral_and_counts_its_steps():
     for s in (a, b):
         s.set_porosity(0.75, pert, 50.0)
         s.init(None, u0)
-    tx, ty, flags, ran = a.autotune(2)
-    assert ran == 12 and a.time == 12  # 3 tiled + 3 flat candidates
+    launch = a.autotune(2)
+    # 3 tiled + 3 flat single-step candidates, two-step tiles of 1, 2, 4 rows x 8, 32, 64 planes
+    assert launch.steps_run == 30 and a.time == 30
     a.step(7)
-    b.step(19)
+    b.step(37)
     assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
     # same size class again: cached, no steps
-    assert b.autotune(2) == (tx, ty, flags, 0)
+    assert b.autotune(2) == launch._replace(steps_run=0)
     a.close()
     b.close()
 
@@ -245,8 +246,9 @@ def test_d3q19_256_full_run_in_bench_launch_vs_oracle_samples(dtype):
     s = vanse.Solver(w.lattice, w.dims, w.tau, dtype)
     s.set_porosity(w.eps_mean, torch.from_numpy(w.eps_pert()).cuda(), w.period)
     s.init(None, torch.from_numpy(np.ascontiguousarray(w.u0())).cuda())
-    _, _, _, ran = s.autotune(4)
-    s.step(w.steps - ran)
+    launch = s.autotune(4)
+    print("launch", launch)
+    s.step(w.steps - launch.steps_run)
     assert s.time == w.steps
     rho, p, u = (t.cpu().numpy() for t in s.moments())
     s.close()
