@@ -462,7 +462,9 @@ __global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__re
 // eps_combine, collide) and the intermediate values pass through the storage
 // encoding as they would through HBM, so one launch is bitwise equal to two
 // single steps.
-template <class L, int MODE, int IPT, int HPT>
+// NXC / TYC: nx and fty as compile-time constants (0: read from a), so that
+// the common tile shapes fold their index arithmetic.
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC>
 __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
 {
     static_assert(L::D == 3, "two-step launch: 3-D lattices only");
@@ -470,13 +472,16 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
     using T = typename St::T;
     using R = typename St::R;
     constexpr int Q = L::Q;
+    // every thread owns one interior cell per IPT (no repeats): stores need no
+    // trash slot
+    constexpr bool EXACT = NXC > 0 && TYC > 0 && NXC * TYC == IPT * kFusedThreads;
     constexpr int RING = 5;                 // pert planes p-2 .. p+2
     constexpr int PPT = (5 * HPT + 2) / 3;  // pert values per thread and plane
     extern __shared__ __align__(16) unsigned char fused_lds[];
 
-    const int nx = a.geo.nx, ny = a.geo.ny, nz = a.geo.nz, nxy = a.geo.nxy;
+    const int nx = NXC ? NXC : a.geo.nx, ny = a.geo.ny, nz = a.geo.nz, nxy = a.geo.nxy;
     const long long S = a.geo.stride;
-    const int TY = (int)a.fty;
+    const int TY = TYC ? TYC : (int)a.fty;
     const int NI = nx * TY;          // interior cells of one plane of the tile
     const int HC = NI + 2 * nx;      // cells of one plane with the two outer rows
     const int PR = TY + 4;           // pert rows per plane: y0-2 .. y0+TY+1
@@ -502,25 +507,28 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
     auto zmod = [&](int v) { return (v + 3 * nz) % nz; };
     // wave-uniform x-row of a cell index of the tile (waves never straddle rows)
     auto row_of = [&](int idx) {
-        return (int)__builtin_amdgcn_readfirstlane(fdiv((unsigned)idx, a.fd_nx));
+        const unsigned r = NXC ? (unsigned)idx / (unsigned)NXC : fdiv((unsigned)idx, a.fd_nx);
+        return (int)__builtin_amdgcn_readfirstlane(r);
     };
-    // ring slot of plane q (q >= z0 - 2)
-    auto slot = [&](int q) { return (q - (z0 - 2)) % RING; };
-    // pert of tile row r (= y - y0 + 2) of plane q, from the ring
-    auto pring = [&](int q, int r, int x) { return ring[(slot(q) * PR + r) * nx + x]; };
+    // Ring slot s holds the pert rows of one plane at ring + s * PC; plane q
+    // lives in slot (q - z0 + 2) mod 5.  The loop keeps the slots of planes
+    // p-2 .. p+2 in wave-uniform registers and rotates them per plane.
     // phi stencil, external + per-cell force and collision of one cell at
-    // (x, y, z) (y, z wave-uniform; r = y - y0 + 2 its ring row, q its plane
-    // index before wrapping) on the decoded values v, at modulation mm
-    auto update = [&](R (&v)[Q], int x, int y, int r, int q, int z, R mm) {
+    // (x, y, z) (y, z wave-uniform; r = y - y0 + 2 its ring row; rm, r0, rp
+    // the ring planes of z - 1, z, z + 1) on the decoded values v, at
+    // modulation mm
+    auto update = [&](R (&v)[Q], int x, int y, int r, const R *rm, const R *r0, const R *rp,
+                      int z, R mm) {
         const int xm = (x == 0 ? nx : x) - 1, xp = (x + 1 == nx) ? 0 : x + 1;
+        const R *row = r0 + r * nx;
         R e[7];
-        e[0] = phi_of(em, mm, pring(q, r, x));
-        e[1] = phi_of(em, mm, pring(q, r, xp));
-        e[2] = phi_of(em, mm, pring(q, r, xm));
-        e[3] = phi_of(em, mm, pring(q, r + 1, x));
-        e[4] = phi_of(em, mm, pring(q, r - 1, x));
-        e[5] = phi_of(em, mm, pring(q + 1, r, x));
-        e[6] = phi_of(em, mm, pring(q - 1, r, x));
+        e[0] = phi_of(em, mm, row[x]);
+        e[1] = phi_of(em, mm, row[xp]);
+        e[2] = phi_of(em, mm, row[xm]);
+        e[3] = phi_of(em, mm, row[nx + x]);
+        e[4] = phi_of(em, mm, row[x - nx]);
+        e[5] = phi_of(em, mm, rp[r * nx + x]);
+        e[6] = phi_of(em, mm, rm[r * nx + x]);
         R I, gx, gy, gz;
         eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
         R Fex = R(a.F[0]), Fey = R(a.F[1]), Fez = R(a.F[2]);
@@ -561,11 +569,11 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
             ph[j] = ld<R, false>(pert + (qz * nxy + y * nx), (unsigned)x * (unsigned)sizeof(R));
         });
     };
-    auto store_pert = [&](const R (&ph)[PPT], int q) {
+    auto store_pert = [&](const R (&ph)[PPT], int s) {
         static_for<0, PPT>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             const int idx = min(tid + j * kFusedThreads, PC - 1);
-            ring[slot(q) * PC + idx] = ph[j];  // repeats write the same value
+            ring[s * PC + idx] = ph[j];  // repeats write the same value
         });
     };
 
@@ -582,16 +590,21 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
     T *__restrict__ trash = static_cast<T *>(a.trash);
     for (int q = z0 - 2; q <= z0; ++q) {
         load_pert(ph, q);
-        store_pert(ph, q);
+        store_pert(ph, q - (z0 - 2));
     }
     load_pert(ph, z0 + 1);
     load_plane(raw, z0 - 1);
     static_for<0, IPT * Q>([&](auto) { st<T, false>(trash, 0u, T(0)); });
 
+    int s0 = 1;  // ring slot of plane p
     for (int p = z0 - 1; p <= z1; ++p) {
         const int pz = wrap(p, nz);
+        const int sp1 = s0 == RING - 1 ? 0 : s0 + 1, sp2 = sp1 == RING - 1 ? 0 : sp1 + 1;
+        const int sm1 = s0 == 0 ? RING - 1 : s0 - 1, sm2 = sm1 == 0 ? RING - 1 : sm1 - 1;
+        const R *ring_m2 = ring + sm2 * PC, *ring_m1 = ring + sm1 * PC;
+        const R *ring_0 = ring + s0 * PC, *ring_p1 = ring + sp1 * PC;
         __syncthreads();  // the slab and the ring slot of plane p - 3 are free
-        store_pert(ph, p + 2);
+        store_pert(ph, sp2);
         static_for<0, HPT>([&](auto hc) {
             constexpr int h = decltype(hc)::value;
             const int idx = min(tid + h * kFusedThreads, HC - 1);
@@ -602,14 +615,15 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
                 constexpr int i = decltype(ic)::value;
                 v[i] = St::decode(raw[h][i]);
             });
-            update(v, x, wrap(y0 + hr - 1, ny), hr + 1, p, pz, R(a.m));
+            update(v, x, wrap(y0 + hr - 1, ny), hr + 1, ring_m1, ring_0, ring_p1, pz, R(a.m));
+            // destination rows hr - 1 + cy of the slab and wrapped columns x + cx
+            const int Ro[3] = {(hr - 2) * nx, (hr - 1) * nx, hr * nx};
+            const int Xd[3] = {(x == 0 ? nx : x) - 1, x, (x + 1 == nx) ? 0 : x + 1};
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 const int r = hr - 1 + L::cy[i];
-                if ((unsigned)r < (unsigned)TY) {  // wave-uniform
-                    const int xd = wrap(x + L::cx[i], nx);
-                    slab[i * NI + r * nx + xd] = St::encode(v[i]);
-                }
+                if ((unsigned)r < (unsigned)TY)  // wave-uniform
+                    slab[i * NI + Ro[L::cy[i] + 1] + Xd[L::cx[i] + 1]] = St::encode(v[i]);
             });
         });
         __syncthreads();  // slab of plane p and ring plane p + 2 complete
@@ -617,6 +631,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
         load_plane(raw, p + 1);
         // interior plane p - 1 is completed from p = z0 + 1 on; before that the
         // work is done on plane z0 (in range) and its results are discarded
+        // (the ring slots it reads may not hold data yet)
         const int z = max(p - 1, z0);
         static_for<0, IPT>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
@@ -637,15 +652,27 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
                 else if constexpr (L::cz[i] == 0) w[i] = mid[k][i];
                 else w[i] = t[i];
             });
-            update(w, x, y, r + 2, z, z, R(a.m2));
+            update(w, x, y, r + 2, ring_m2, ring_m1, ring_0, z, R(a.m2));
+            // push to x + xi_i: wrapped rows (wave-uniform) and columns of a.f2
+            const int Yo[3] = {((y == 0 ? ny : y) - 1) * nx, y * nx,
+                               ((y + 1 == ny) ? 0 : y + 1) * nx};
+            const int Zo[3] = {((z == 0 ? nz : z) - 1) * nxy, z * nxy,
+                               ((z + 1 == nz) ? 0 : z + 1) * nxy};
+            const unsigned Xo[3] = {(unsigned)((x == 0 ? nx : x) - 1) * (unsigned)sizeof(T),
+                                    (unsigned)x * (unsigned)sizeof(T),
+                                    (unsigned)((x + 1 == nx) ? 0 : x + 1) * (unsigned)sizeof(T)};
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                const int yd = wrap(y + L::cy[i], ny);
-                const int zd = wrap(z + L::cz[i], nz);
-                const int xd = wrap(x + L::cx[i], nx);
-                T *base = own ? dst + i * S + (zd * nxy + yd * nx) : trash;
-                st<T, false>(base, own ? (unsigned)xd * (unsigned)sizeof(T) : 0u,
-                             St::encode(w[i]));
+                T *row = dst + i * S + (Zo[L::cz[i] + 1] + Yo[L::cy[i] + 1]);
+                if constexpr (EXACT) {
+                    // every thread owns its cell; the leading iterations write
+                    // their discarded results into the slots this thread
+                    // rewrites when it completes plane z0
+                    st<T, false>(row, Xo[L::cx[i] + 1], St::encode(w[i]));
+                } else {
+                    st<T, false>(own ? row : trash, own ? Xo[L::cx[i] + 1] : 0u,
+                                 St::encode(w[i]));
+                }
             });
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
@@ -657,6 +684,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
                 }
             });
         });
+        s0 = sp1;
     }
 }
 
@@ -970,15 +998,21 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
     const unsigned nzb = (unsigned)((a.geo.nz + (int)a.fsz - 1) / (int)a.fsz);
     const unsigned nblocks = a.fnyb * nzb;
     hipError_t rc = hipErrorInvalidValue;
-    auto go = [&](auto lat, auto mode, auto ic, auto hc) {
+    bool launched = false;
+    const int nx = a.geo.nx, ty = (int)a.fty;
+    // one instantiation: IPT, HPT and (0 = runtime) compile-time nx / fty
+    auto go = [&](auto lat, auto mode, auto ic, auto hc, auto nxc, auto tyc) {
         using L = decltype(lat);
         constexpr int M = decltype(mode)::value;
         constexpr int I = decltype(ic)::value;
         constexpr int H = decltype(hc)::value;
+        constexpr int NXC = decltype(nxc)::value;
+        constexpr int TYC = decltype(tyc)::value;
         constexpr int LAT = std::is_same<L, D3Q19>::value ? 1 : 2;
         if constexpr (fused_compiled(LAT, M, I, H)) {
-            if (I != ipt || H != hpt) return;
-            auto *fn = &fused2_kernel<L, M, I, H>;
+            if (launched || I != ipt || H != hpt) return;
+            if (NXC && (NXC != nx || TYC != ty)) return;
+            auto *fn = &fused2_kernel<L, M, I, H, NXC, TYC>;
             // slabs above 64 KiB need the kernel's LDS limit raised, once per device
             static std::atomic<unsigned long long> raised{0};
             int dev = 0;
@@ -992,19 +1026,33 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
             }
             fn<<<nblocks, kFusedThreads, lds, s.stream>>>(a);
             rc = hipGetLastError();
+            launched = true;
         }
     };
     auto shapes = [&](auto lat, auto mode) {
+        using L = decltype(lat);
+        using C0 = std::integral_constant<int, 0>;
         using C1 = std::integral_constant<int, 1>;
         using C2 = std::integral_constant<int, 2>;
         using C3 = std::integral_constant<int, 3>;
         using C4 = std::integral_constant<int, 4>;
-        go(lat, mode, C1{}, C1{});
-        go(lat, mode, C1{}, C2{});
-        go(lat, mode, C1{}, C3{});
-        go(lat, mode, C2{}, C2{});
-        go(lat, mode, C2{}, C3{});
-        go(lat, mode, C2{}, C4{});
+        using C128 = std::integral_constant<int, 128>;
+        using C256 = std::integral_constant<int, 256>;
+        // compiled shapes of the common tiles: 256-wide rows x 2 or 4 rows,
+        // 128-wide rows x 4 rows (D3Q19); 256-wide x 2 rows (D3Q27)
+        if constexpr (std::is_same<L, D3Q19>::value) {
+            go(lat, mode, C2{}, C3{}, C256{}, C4{});
+            go(lat, mode, C1{}, C2{}, C256{}, C2{});
+            go(lat, mode, C1{}, C2{}, C128{}, C4{});
+        } else {
+            go(lat, mode, C1{}, C2{}, C256{}, C2{});
+        }
+        go(lat, mode, C1{}, C1{}, C0{}, C0{});
+        go(lat, mode, C1{}, C2{}, C0{}, C0{});
+        go(lat, mode, C1{}, C3{}, C0{}, C0{});
+        go(lat, mode, C2{}, C2{}, C0{}, C0{});
+        go(lat, mode, C2{}, C3{}, C0{}, C0{});
+        go(lat, mode, C2{}, C4{}, C0{}, C0{});
     };
     auto modes = [&](auto lat) {
         if (s.mode == MODE_F64) shapes(lat, std::integral_constant<int, MODE_F64>{});
