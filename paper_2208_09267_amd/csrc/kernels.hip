@@ -40,18 +40,24 @@ __device__ __forceinline__ void static_for(Fn &&fn)
     }
 }
 
-// a*x + b*y + c*z for compile-time a, b, c in {-1, 0, 1}; zero terms vanish.
-template <int A, int B, int C, class R>
-__device__ __forceinline__ R dot3(R x, R y, R z)
+// a*x + b*y + c*z for compile-time a, b, c in {-1, 0, 1}; zero terms vanish
+// and the first nonzero term starts the sum (no 0 + x to evaluate).
+template <int B, int C, class R>
+__device__ __forceinline__ R add_terms(R s, R y, R z)
 {
-    R s = R(0);
-    if constexpr (A == 1) s = s + x;
-    if constexpr (A == -1) s = s - x;
     if constexpr (B == 1) s = s + y;
     if constexpr (B == -1) s = s - y;
     if constexpr (C == 1) s = s + z;
     if constexpr (C == -1) s = s - z;
     return s;
+}
+template <int A, int B, int C, class R>
+__device__ __forceinline__ R dot3(R x, R y, R z)
+{
+    if constexpr (A != 0) return add_terms<B, C>(A == 1 ? x : -x, y, z);
+    else if constexpr (B != 0) return add_terms<0, C>(B == 1 ? y : -y, y, z);
+    else if constexpr (C != 0) return C == 1 ? z : -z;
+    else return R(0);
 }
 
 // Storage of one population: T is the raw element type in HBM, R the
@@ -171,10 +177,7 @@ __device__ __forceinline__ void eps_combine(const R (&e)[7], R wq, R n2, int qma
                                             R &gx, R &gy, R &gz)
 {
     R S = R(0);
-    if (qmask & 1) {
-        S = S + e[1];
-        S = S + e[2];
-    }
+    if (qmask & 1) S = e[1] + e[2];
     if (qmask & 2) {
         S = S + e[3];
         S = S + e[4];
@@ -227,6 +230,15 @@ __device__ __forceinline__ void eps_ops(const R *__restrict__ pert, R eps_mean, 
 // b9 = 9 k, c3 = 3 omega M0, d3 = 3 k, k = 1 - omega/2, W = w_i (or 1 when
 // the stored value is scaled by 1/w_i), and E = M0 (1 - 3/2 uu) for f, or
 // dM0 - 3/2 uu M0 for the shifted values.
+// First direction 1 .. H whose velocity has a nonzero component `axis`.
+template <class L, int AXIS>
+constexpr int first_dir()
+{
+    for (int i = 1; i <= L::H; ++i)
+        if ((AXIS == 0 ? L::cx[i] : AXIS == 1 ? L::cy[i] : L::cz[i]) != 0) return i;
+    return 0;
+}
+
 template <class L, int MODE, class R>
 __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R omega,
                                         R fcoef, R Fex, R Fey, R Fez)
@@ -245,9 +257,19 @@ __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R o
         const R dm = v[i] - v[o];
         constexpr R w = St::scaled ? R(L::w[i]) : R(1);
         s0 = s0 + w * sp;
-        if constexpr (L::cx[i] != 0) jx = jx + R(L::cx[i]) * w * dm;
-        if constexpr (L::cy[i] != 0) jy = jy + R(L::cy[i]) * w * dm;
-        if constexpr (L::cz[i] != 0) jz = jz + R(L::cz[i]) * w * dm;
+        // the first direction with a nonzero component starts each sum
+        if constexpr (L::cx[i] != 0) {
+            const R t = R(L::cx[i]) * w * dm;
+            if constexpr (i == first_dir<L, 0>()) jx = t; else jx = jx + t;
+        }
+        if constexpr (L::cy[i] != 0) {
+            const R t = R(L::cy[i]) * w * dm;
+            if constexpr (i == first_dir<L, 1>()) jy = t; else jy = jy + t;
+        }
+        if constexpr (L::cz[i] != 0) {
+            const R t = R(L::cz[i]) * w * dm;
+            if constexpr (i == first_dir<L, 2>()) jz = t; else jz = jz + t;
+        }
     });
     const R M0 = St::shifted ? R(1) + s0 : s0;
     const R rho = M0 / I;               // eq. density
