@@ -19,7 +19,6 @@ on a bounded number of steps of the same workload on the host cores.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -45,11 +44,8 @@ def kernel_name(variant, two_step, lattice="D3Q19"):
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for name in ("kernels.hip", "lattice.h", "internal.h"):
-        with open(os.path.join(ROOT, "paper_2208_09267_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2208_09267_amd.rocprof_summary import kernel_source_hash as h
+    return h()
 
 
 def measured_traffic(variant, kernel):
@@ -72,7 +68,7 @@ def measured_traffic(variant, kernel):
 # --fixed-launch, e.g. under a counter profiler that perturbs timing)
 # (tile_x, tile_y, flat, two-step rows, two-step planes)
 FIXED_LAUNCH = {"fp32_shifted": (1024, 1, True, 4, 64), "fp64": (512, 1, True, 2, 64),
-                "fp16_shifted": (256, 4, False, 0, 0)}
+                "fp16_shifted": (256, 4, False, 4, 64)}
 SINGLE_LAUNCH = {"fp32_shifted": (1024, 1, True, 0, 0), "fp64": (512, 1, True, 0, 0),
                  "fp16_shifted": (256, 4, False, 0, 0)}
 

