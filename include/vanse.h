@@ -229,14 +229,20 @@ int vanse_set_tile(vanse_t h, int tile_x, int tile_y);
  * each end of the segment).  vanse_step takes every pair of steps that
  * starts at an even level this way; a step left over (odd level, or odd n)
  * uses the single-step kernel.  Results are bitwise identical to single
- * steps.  Requires nx a multiple of 64, ny a multiple of rows, planes >= 1,
- * and a tile shape compiled into the library (the shapes whose registers
- * fit without spilling): with I = ceil(nx * rows / 512) interior and
- * H = ceil(nx * (rows + 2) / 512) halo cells per thread,
+ * steps.  Requires 1 <= rows <= ny, planes >= 1, and a tile shape compiled
+ * into the library (the shapes whose registers fit without spilling): with
+ * I = ceil(nx * rows / 512) interior and H = ceil(nx * (rows + 2) / 512)
+ * halo cells per thread, when nx is a multiple of 64 and rows divides ny
  *   D3Q19, FP32/FP16 storage: I <= 2 and H <= I + 2
  *   D3Q19, FP64: I = 1 and H <= 2
  *   D3Q27, FP32/FP16 storage: I = 1 and H <= 3, or I = 2 and H = 2
- *   D3Q27, FP64: none (single steps only),
+ *   D3Q27, FP64: none (single steps only);
+ * otherwise (the general tile: any nx, a shorter last tile in y, and
+ * nx * ny * nz * 8 < 2^32)
+ *   D3Q19, FP32/FP16 storage: I = 1 and H <= 3, or I = 2 and H = 2
+ *   D3Q19, FP64: I = 1 and H = 1
+ *   D3Q27, FP32/FP16 storage: I = 1 and H <= 2
+ *   D3Q27, FP64: none;
  * and the block's LDS (Q * nx * rows stored populations plus 5 * (rows + 4)
  * * nx perturbation values) within 160 KiB.
  * rows = 0 switches the launch off and frees the second array.

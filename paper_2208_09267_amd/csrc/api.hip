@@ -91,7 +91,7 @@ StepArgs step_args(const Solver &s, int64_t n)
     a.m2 = modulation(n + 1, s.period);
     a.fty = (unsigned)std::max(s.fused_rows, 1);
     a.fsz = (unsigned)std::max(s.fused_planes, 1);
-    a.fnyb = (unsigned)(s.geo.ny / (int)a.fty);
+    a.fnyb = (unsigned)((s.geo.ny + (int)a.fty - 1) / (int)a.fty);
     a.fd_fnyb = make_fastdiv(std::max(a.fnyb, 1u));
     a.trash = s.scratch ? s.scratch + kTrashSlot : nullptr;
     return a;
@@ -446,15 +446,12 @@ int vanse_set_fused(vanse_t h, int rows, int planes)
     if (s.d != 3) return fail(&s, VANSE_EINVAL, "vanse_set_fused: 3-D lattices only");
     if (rows < 0 || planes < 1)
         return fail(&s, VANSE_EINVAL, "vanse_set_fused: rows must be >= 0 and planes >= 1");
-    if (s.geo.ny % rows != 0)
-        return fail(&s, VANSE_EINVAL, "vanse_set_fused: rows must divide ny");
-    const size_t lds = vanse::fused_lds_bytes(s.q, s.mode, s.geo.nx, rows);
-    if (!vanse::fused_shape(s.lattice, s.mode, s.geo.nx, rows, nullptr, nullptr) ||
-        lds > (size_t)vanse::kFusedMaxLds)
+    if (rows > s.geo.ny)
+        return fail(&s, VANSE_EINVAL, "vanse_set_fused: rows must be <= ny");
+    if (!vanse::fused_shape(s.lattice, s.mode, s.geo, rows, nullptr))
         return fail(&s, VANSE_EINVAL,
                     "vanse_set_fused: no compiled tile of nx = " + std::to_string(s.geo.nx) +
-                        " x " + std::to_string(rows) +
-                        " rows for this lattice and dtype (nx must be a multiple of 64)");
+                        " x " + std::to_string(rows) + " rows for this lattice and dtype");
     if (!s.f_alt) {
         if ((e = hipMalloc(&s.f_alt, s.f_bytes)) != hipSuccess) {
             s.f_alt = nullptr;
@@ -514,9 +511,7 @@ int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int
             const int planes[3] = {8, 32, 64};
             for (int r : rows)
                 for (int p : planes) {
-                    const size_t lds = vanse::fused_lds_bytes(s.q, s.mode, s.geo.nx, r);
-                    if (s.geo.ny % r == 0 && lds <= (size_t)vanse::kFusedMaxLds &&
-                        vanse::fused_shape(s.lattice, s.mode, s.geo.nx, r, nullptr, nullptr))
+                    if (r <= s.geo.ny && vanse::fused_shape(s.lattice, s.mode, s.geo, r, nullptr))
                         cand.push_back({256, 1, 1, r, p});
                 }
         }

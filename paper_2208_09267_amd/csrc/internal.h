@@ -130,9 +130,24 @@ constexpr bool fused_compiled(int lattice, int mode, int ipt, int hpt)
     if (mode == MODE_F64) return ipt == 1 && hpt <= 2;
     return ipt <= 2 && hpt <= ipt + 2;
 }
-// Per-thread work counts of the two-step launch for a tile of `rows` full
-// x-rows; false if the lattice has no such compiled shape.
-bool fused_shape(int lattice, int mode, int nx, int rows, int *ipt, int *hpt);
+// The same for the general tile (any nx, shorter last tile), whose rows and
+// row bases are per lane.
+constexpr bool fused_compiled_gen(int lattice, int mode, int ipt, int hpt)
+{
+    if (lattice == 0 || ipt < 1 || hpt < ipt) return false;
+    if (lattice == 2) return mode != MODE_F64 && ipt == 1 && hpt <= 2;
+    if (mode == MODE_F64) return ipt == 1 && hpt == 1;
+    return ipt == 1 ? hpt <= 3 : (ipt == 2 && hpt == 2);
+}
+// Two-step launch variant of a tile of `rows` full x-rows: ipt interior and
+// hpt halo-plane cells per thread; gen: the general tile (nx not a multiple
+// of 64 or rows not dividing ny; needs every array's byte size below 2^32).
+struct FusedShape {
+    int ipt = 0, hpt = 0;
+    bool gen = false;
+};
+// false if the lattice/dtype has no such compiled shape or the LDS is too large.
+bool fused_shape(int lattice, int mode, const Geometry &g, int rows, FusedShape *out);
 // LDS of one block of the two-step launch: the population slab and the ring
 // of 5 perturbation planes of rows + 4 x-rows.
 size_t fused_lds_bytes(int q, int mode, int nx, int rows);

@@ -484,10 +484,15 @@ __global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__re
 // eps_combine, collide) and the intermediate values pass through the storage
 // encoding as they would through HBM, so one launch is bitwise equal to two
 // single steps.
-// NXC / TYC: nx and fty as compile-time constants (0: read from a), so that
-// the common tile shapes fold their index arithmetic.
-template <class L, int MODE, int IPT, int HPT, int NXC, int TYC>
-__global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
+// One tile (number b, y-fastest) of a two-step launch from a.f to a.f2 at
+// modulations a.m, a.m2.  NXC / TYC: nx and fty as compile-time constants
+// (0: read from a), so that the common tile shapes fold their index
+// arithmetic.  GEN: any nx (waves may straddle x-rows: rows and row bases are
+// per lane, accesses use 32-bit element offsets, which the host allows only
+// when every array's byte size fits 32 bits) and a shorter last tile when fty
+// does not divide ny; otherwise nx is a multiple of 64 and fty divides ny.
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN>
+__device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
 {
     static_assert(L::D == 3, "two-step launch: 3-D lattices only");
     using St = Storage<MODE>;
@@ -496,14 +501,16 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
     constexpr int Q = L::Q;
     // every thread owns one interior cell per IPT (no repeats): stores need no
     // trash slot
-    constexpr bool EXACT = NXC > 0 && TYC > 0 && NXC * TYC == IPT * kFusedThreads;
+    constexpr bool EXACT = !GEN && NXC > 0 && TYC > 0 && NXC * TYC == IPT * kFusedThreads;
     constexpr int RING = 5;                 // pert planes p-2 .. p+2
     constexpr int PPT = (5 * HPT + 2) / 3;  // pert values per thread and plane
     extern __shared__ __align__(16) unsigned char fused_lds[];
 
     const int nx = NXC ? NXC : a.geo.nx, ny = a.geo.ny, nz = a.geo.nz, nxy = a.geo.nxy;
     const long long S = a.geo.stride;
-    const int TY = TYC ? TYC : (int)a.fty;
+    const unsigned bz = fdiv(b, a.fd_fnyb);
+    const int y0 = (int)(b - bz * a.fnyb) * (TYC ? TYC : (int)a.fty);
+    const int TY = TYC ? TYC : (GEN ? min((int)a.fty, ny - y0) : (int)a.fty);
     const int NI = nx * TY;          // interior cells of one plane of the tile
     const int HC = NI + 2 * nx;      // cells of one plane with the two outer rows
     const int PR = TY + 4;           // pert rows per plane: y0-2 .. y0+TY+1
@@ -511,17 +518,6 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
     T *__restrict__ slab = reinterpret_cast<T *>(fused_lds);
     R *__restrict__ ring =
         reinterpret_cast<R *>(fused_lds + ((size_t)Q * NI * sizeof(T) + 15) / 16 * 16);
-    // Tiles are numbered y-fastest, and each of the 8 XCDs, to which the
-    // hardware deals blocks round-robin, gets one contiguous range of tiles:
-    // y-neighbours run on the same XCD at the same time, so the rows both
-    // re-read can come from its L2 (measured 3% faster on 256^3).
-    unsigned b = blockIdx.x;
-    {
-        const unsigned q = gridDim.x >> 3, r = gridDim.x & 7, xcd = b & 7, k = b >> 3;
-        b = (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
-    }
-    const unsigned bz = fdiv(b, a.fd_fnyb);
-    const int y0 = (int)(b - bz * a.fnyb) * TY;
     const int z0 = (int)bz * (int)a.fsz;
     const int z1 = min(z0 + (int)a.fsz, nz);
     const T *__restrict__ src = static_cast<const T *>(a.f);
@@ -536,11 +532,14 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
     // periodic plane index for any v >= -3 (the prologue and the prefetch
     // reach 2 planes below and 3 above the segment, also when nz < 3)
     auto zmod = [&](int v) { return (v + 3 * nz) % nz; };
-    // wave-uniform x-row of a cell index of the tile (waves never straddle rows)
+    // x-row of a cell index of the tile: wave-uniform unless GEN
     auto row_of = [&](int idx) {
         const unsigned r = NXC ? (unsigned)idx / (unsigned)NXC : fdiv((unsigned)idx, a.fd_nx);
-        return (int)__builtin_amdgcn_readfirstlane(r);
+        if constexpr (GEN) return (int)r;
+        else return (int)__builtin_amdgcn_readfirstlane(r);
     };
+    // element offset -> byte offset (GEN: 32-bit, checked on the host)
+    auto boff = [](int elem, unsigned size) { return (unsigned)elem * size; };
     // Ring slot s holds the pert rows of one plane at ring + s * PC; plane q
     // lives in slot (q - z0 + 2) mod 5.  The loop keeps the slots of planes
     // p-2 .. p+2 in wave-uniform registers and rotates them per plane.
@@ -564,11 +563,18 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
         eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
         R Fex = R(a.F[0]), Fey = R(a.F[1]), Fez = R(a.F[2]);
         if (fc) {
-            const R *row = fc + (z * nxy + y * nx);
-            const unsigned ox = (unsigned)x * (unsigned)sizeof(R);
-            Fex = Fex + ld<R, false>(row, ox);
-            Fey = Fey + ld<R, false>(row + S, ox);
-            Fez = Fez + ld<R, false>(row + 2 * S, ox);
+            if constexpr (GEN) {
+                const unsigned o = boff(z * nxy + y * nx + x, sizeof(R));
+                Fex = Fex + ld<R, false>(fc, o);
+                Fey = Fey + ld<R, false>(fc + S, o);
+                Fez = Fez + ld<R, false>(fc + 2 * S, o);
+            } else {
+                const R *row = fc + (z * nxy + y * nx);
+                const unsigned ox = (unsigned)x * (unsigned)sizeof(R);
+                Fex = Fex + ld<R, false>(row, ox);
+                Fey = Fey + ld<R, false>(row + S, ox);
+                Fez = Fez + ld<R, false>(row + 2 * S, ox);
+            }
         }
         collide<L, MODE, R>(v, I, gx, gy, gz, R(a.omega), R(a.fcoef), Fex, Fey, Fez);
     };
@@ -581,11 +587,19 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
             const int hr = row_of(idx);
             const int x = idx - hr * nx;
             const int y = wrap(y0 + hr - 1, ny);
-            const T *base = src + (pz * nxy + y * nx);
-            static_for<0, Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                raw[h][i] = ld<T, false>(base + i * S, (unsigned)x * (unsigned)sizeof(T));
-            });
+            if constexpr (GEN) {
+                const unsigned o = boff(pz * nxy + y * nx + x, sizeof(T));
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    raw[h][i] = ld<T, false>(src + i * S, o);
+                });
+            } else {
+                const T *base = src + (pz * nxy + y * nx);
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    raw[h][i] = ld<T, false>(base + i * S, (unsigned)x * (unsigned)sizeof(T));
+                });
+            }
         });
     };
     // pert of the PR ring rows of plane q: into registers, then into the ring
@@ -597,7 +611,10 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
             const int r = row_of(idx);
             const int x = idx - r * nx;
             const int y = ((y0 + r - 2) % ny + ny) % ny;
-            ph[j] = ld<R, false>(pert + (qz * nxy + y * nx), (unsigned)x * (unsigned)sizeof(R));
+            if constexpr (GEN)
+                ph[j] = ld<R, false>(pert, boff(qz * nxy + y * nx + x, sizeof(R)));
+            else
+                ph[j] = ld<R, false>(pert + (qz * nxy + y * nx), (unsigned)x * (unsigned)sizeof(R));
         });
     };
     auto store_pert = [&](const R (&ph)[PPT], int s) {
@@ -653,7 +670,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 const int r = hr - 1 + L::cy[i];
-                if ((unsigned)r < (unsigned)TY)  // wave-uniform
+                if ((unsigned)r < (unsigned)TY)  // wave-uniform unless GEN
                     slab[i * NI + Ro[L::cy[i] + 1] + Xd[L::cx[i] + 1]] = St::encode(v[i]);
             });
         });
@@ -666,7 +683,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
         const int z = max(p - 1, z0);
         static_for<0, IPT>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const bool own = tid + k * kFusedThreads < NI && p > z0;  // wave-uniform
+            const bool own = tid + k * kFusedThreads < NI && p > z0;  // wave-uniform unless GEN
             const int cell = min(tid + k * kFusedThreads, NI - 1);
             R t[Q];
             static_for<0, Q>([&](auto ic) {
@@ -695,7 +712,11 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 T *row = dst + i * S + (Zo[L::cz[i] + 1] + Yo[L::cy[i] + 1]);
-                if constexpr (EXACT) {
+                if constexpr (GEN) {
+                    const unsigned o = boff(Zo[L::cz[i] + 1] + Yo[L::cy[i] + 1], sizeof(T)) +
+                                       Xo[L::cx[i] + 1];
+                    st<T, false>(own ? dst + i * S : trash, own ? o : 0u, St::encode(w[i]));
+                } else if constexpr (EXACT) {
                     // every thread owns its cell; the leading iterations write
                     // their discarded results into the slots this thread
                     // rewrites when it completes plane z0
@@ -717,6 +738,47 @@ __global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
         });
         s0 = sp1;
     }
+}
+
+
+// Block b of a grid of n blocks -> tile number: the hardware deals blocks
+// round-robin over the 8 XCDs; this gives each XCD one contiguous range of
+// tiles, so y-neighbour tiles run on the same XCD at the same time and the
+// rows both re-read can come from its L2.
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned b, unsigned n)
+{
+    const unsigned q = n >> 3, r = n & 7, xcd = b & 7, k = b >> 3;
+    return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
+}
+
+// Two-step launch of one solve.
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN>
+__global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
+{
+    fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN>(a, xcd_contiguous(blockIdx.x, gridDim.x));
+}
+
+// Two-step launch of many solves (GEN tiles): block b belongs to solve
+// owner[b] (after the XCD-contiguous order), whose tiles are a contiguous
+// range from members[s].block_begin.  Steps j and j + 1 of the chunk
+// (modulations mtab[j][s], mtab[j + 1][s]); swap: the solve's current
+// populations are in its second array (odd launch of a chunk).
+template <class L, int MODE, int IPT, int HPT>
+__global__ void __launch_bounds__(kFusedThreads)
+    batch_fused2_kernel(const BatchMember *__restrict__ members, const unsigned *__restrict__ owner,
+                        const double *__restrict__ mtab, int j, int count, int swap)
+{
+    const unsigned b = xcd_contiguous(blockIdx.x, gridDim.x);
+    const unsigned s = owner[b];
+    StepArgs a = members[s].a;
+    a.m = mtab[(long long)j * count + s];
+    a.m2 = mtab[(long long)(j + 1) * count + s];
+    if (swap) {
+        void *t = a.f;
+        a.f = a.f2;
+        a.f2 = t;
+    }
+    fused2_tile<L, MODE, IPT, HPT, 0, 0, true>(a, b - members[s].block_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1007,43 +1069,59 @@ size_t fused_lds_bytes(int q, int mode, int nx, int rows)
     return slab + ring;
 }
 
-bool fused_shape(int lattice, int mode, int nx, int rows, int *ipt, int *hpt)
+bool fused_shape(int lattice, int mode, const Geometry &g, int rows, FusedShape *out)
 {
-    if (nx < 64 || nx % 64 != 0 || rows < 1) return false;  // waves must not straddle x-rows
+    const int nx = g.nx;
+    if (rows < 1 || rows > g.ny) return false;
     const long long ni = (long long)nx * rows, hc = ni + 2ll * nx;
     const long long i = (ni + kFusedThreads - 1) / kFusedThreads;
     const long long h = (hc + kFusedThreads - 1) / kFusedThreads;
     if (i > 4 || h > 8) return false;
-    if (ipt) *ipt = (int)i;
-    if (hpt) *hpt = (int)h;
-    return fused_compiled(lattice, mode, (int)i, (int)h);
+    FusedShape sh;
+    sh.ipt = (int)i;
+    sh.hpt = (int)h;
+    sh.gen = nx % 64 != 0 || g.ny % rows != 0;
+    if (sh.gen) {
+        // 32-bit byte offsets: every population plane, pert and force array
+        if ((long long)g.ncells * 8 >= (1ll << 32)) return false;
+        if (!fused_compiled_gen(lattice, mode, sh.ipt, sh.hpt)) return false;
+    } else if (!fused_compiled(lattice, mode, sh.ipt, sh.hpt)) {
+        return false;
+    }
+    const int q = lattice == 0 ? 9 : (lattice == 1 ? 19 : 27);
+    if (fused_lds_bytes(q, mode, nx, rows) > (size_t)kFusedMaxLds) return false;
+    if (out) *out = sh;
+    return true;
 }
 
 hipError_t launch_fused(const Solver &s, const StepArgs &a)
 {
-    int ipt = 0, hpt = 0;
-    if (!fused_shape(s.lattice, s.mode, a.geo.nx, (int)a.fty, &ipt, &hpt))
-        return hipErrorInvalidValue;
+    FusedShape sh;
+    if (!fused_shape(s.lattice, s.mode, a.geo, (int)a.fty, &sh)) return hipErrorInvalidValue;
+    const int ipt = sh.ipt, hpt = sh.hpt;
+    const bool gen = sh.gen;
     const size_t lds = fused_lds_bytes(s.q, s.mode, a.geo.nx, (int)a.fty);
-    if (lds > (size_t)kFusedMaxLds) return hipErrorInvalidValue;
     const unsigned nzb = (unsigned)((a.geo.nz + (int)a.fsz - 1) / (int)a.fsz);
     const unsigned nblocks = a.fnyb * nzb;
     hipError_t rc = hipErrorInvalidValue;
     bool launched = false;
     const int nx = a.geo.nx, ty = (int)a.fty;
-    // one instantiation: IPT, HPT and (0 = runtime) compile-time nx / fty
-    auto go = [&](auto lat, auto mode, auto ic, auto hc, auto nxc, auto tyc) {
+    // one instantiation: IPT, HPT, (0 = runtime) compile-time nx / fty, GEN
+    auto go = [&](auto lat, auto mode, auto ic, auto hc, auto nxc, auto tyc, auto genc) {
         using L = decltype(lat);
         constexpr int M = decltype(mode)::value;
         constexpr int I = decltype(ic)::value;
         constexpr int H = decltype(hc)::value;
         constexpr int NXC = decltype(nxc)::value;
         constexpr int TYC = decltype(tyc)::value;
+        constexpr bool GEN = decltype(genc)::value;
         constexpr int LAT = std::is_same<L, D3Q19>::value ? 1 : 2;
-        if constexpr (fused_compiled(LAT, M, I, H)) {
-            if (launched || I != ipt || H != hpt) return;
+        constexpr bool compiled =
+            GEN ? (NXC == 0 && fused_compiled_gen(LAT, M, I, H)) : fused_compiled(LAT, M, I, H);
+        if constexpr (compiled) {
+            if (launched || I != ipt || H != hpt || GEN != gen) return;
             if (NXC && (NXC != nx || TYC != ty)) return;
-            auto *fn = &fused2_kernel<L, M, I, H, NXC, TYC>;
+            auto *fn = &fused2_kernel<L, M, I, H, NXC, TYC, GEN>;
             // slabs above 64 KiB need the kernel's LDS limit raised, once per device
             static std::atomic<unsigned long long> raised{0};
             int dev = 0;
@@ -1071,19 +1149,26 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
         using C256 = std::integral_constant<int, 256>;
         // compiled shapes of the common tiles: 256-wide rows x 2 or 4 rows,
         // 128-wide rows x 4 rows (D3Q19); 256-wide x 2 rows (D3Q27)
+        using F = std::false_type;
+        using G = std::true_type;
         if constexpr (std::is_same<L, D3Q19>::value) {
-            go(lat, mode, C2{}, C3{}, C256{}, C4{});
-            go(lat, mode, C1{}, C2{}, C256{}, C2{});
-            go(lat, mode, C1{}, C2{}, C128{}, C4{});
+            go(lat, mode, C2{}, C3{}, C256{}, C4{}, F{});
+            go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{});
+            go(lat, mode, C1{}, C2{}, C128{}, C4{}, F{});
         } else {
-            go(lat, mode, C1{}, C2{}, C256{}, C2{});
+            go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{});
         }
-        go(lat, mode, C1{}, C1{}, C0{}, C0{});
-        go(lat, mode, C1{}, C2{}, C0{}, C0{});
-        go(lat, mode, C1{}, C3{}, C0{}, C0{});
-        go(lat, mode, C2{}, C2{}, C0{}, C0{});
-        go(lat, mode, C2{}, C3{}, C0{}, C0{});
-        go(lat, mode, C2{}, C4{}, C0{}, C0{});
+        go(lat, mode, C1{}, C1{}, C0{}, C0{}, F{});
+        go(lat, mode, C1{}, C2{}, C0{}, C0{}, F{});
+        go(lat, mode, C1{}, C3{}, C0{}, C0{}, F{});
+        go(lat, mode, C2{}, C2{}, C0{}, C0{}, F{});
+        go(lat, mode, C2{}, C3{}, C0{}, C0{}, F{});
+        go(lat, mode, C2{}, C4{}, C0{}, C0{}, F{});
+        go(lat, mode, C1{}, C1{}, C0{}, C0{}, G{});
+        go(lat, mode, C1{}, C2{}, C0{}, C0{}, G{});
+        go(lat, mode, C1{}, C3{}, C0{}, C0{}, G{});
+        go(lat, mode, C2{}, C2{}, C0{}, C0{}, G{});
+        go(lat, mode, C2{}, C3{}, C0{}, C0{}, G{});
     };
     auto modes = [&](auto lat) {
         if (s.mode == MODE_F64) shapes(lat, std::integral_constant<int, MODE_F64>{});

@@ -21,17 +21,24 @@ from paper_2208_09267_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _compiled(lat, dtype, nx, rows):
+def _compiled(lat, dtype, dims, rows):
     """Mirror of the shape rule in vanse_set_fused's documentation."""
+    nx, ny = dims[0], dims[1]
     i = -(-nx * rows // 512)
     h = -(-nx * (rows + 2) // 512)
-    if nx % 64:
+    if rows > ny:
         return False
+    if nx % 64 == 0 and ny % rows == 0:
+        if lat == "D3Q27":
+            return dtype != vanse.FP64 and (h <= 3 if i == 1 else (i == 2 and h == 2))
+        if dtype == vanse.FP64:
+            return i == 1 and h <= 2
+        return i <= 2 and h <= i + 2
     if lat == "D3Q27":
-        return dtype != vanse.FP64 and (h <= 3 if i == 1 else (i == 2 and h == 2))
+        return dtype != vanse.FP64 and i == 1 and h <= 2
     if dtype == vanse.FP64:
-        return i == 1 and h <= 2
-    return i <= 2 and h <= i + 2
+        return i == 1 and h == 1
+    return h <= 3 if i == 1 else (i == 2 and h == 2)
 
 
 def _solver(lat, dims, dtype, seed, force_field=False):
@@ -75,14 +82,18 @@ SHAPES = [("D3Q19", (64, 8, 6), 1, 4), ("D3Q19", (64, 8, 6), 2, 32), ("D3Q19", (
           ("D3Q19", (64, 1, 2), 1, 1), ("D3Q19", (192, 6, 7), 3, 5), ("D3Q19", (256, 4, 9), 4, 4),
           ("D3Q19", (128, 12, 3), 6, 2),
           ("D3Q27", (64, 4, 5), 2, 2), ("D3Q27", (64, 8, 6), 8, 4), ("D3Q27", (128, 6, 4), 3, 3),
-          ("D3Q27", (64, 3, 1), 3, 1)]
+          ("D3Q27", (64, 3, 1), 3, 1),
+          # general tiles: nx not a multiple of 64, rows not dividing ny (shorter last tile)
+          ("D3Q19", (48, 10, 7), 4, 3), ("D3Q19", (33, 17, 5), 5, 2), ("D3Q19", (96, 7, 6), 3, 4),
+          ("D3Q19", (7, 5, 3), 2, 1), ("D3Q19", (1, 1, 1), 1, 1), ("D3Q19", (64, 9, 4), 4, 8),
+          ("D3Q19", (130, 3, 2), 2, 2), ("D3Q27", (40, 6, 5), 4, 3), ("D3Q27", (17, 3, 2), 2, 1)]
 
 
 @pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
 @pytest.mark.parametrize("lat,dims,rows,planes", SHAPES)
 def test_two_step_equals_single_steps_bitwise(lat, dims, rows, planes, dtype):
     print("case", lat, dims, rows, planes, dtype, flush=True)
-    if not _compiled(lat, dtype, dims[0], rows):
+    if not _compiled(lat, dtype, dims, rows):
         s = _solver(lat, dims, dtype, 1)
         with pytest.raises(vanse.VanseError) as e:
             s.set_fused(rows, planes)
@@ -124,7 +135,7 @@ def test_two_step_vs_oracle_every_population():
 def test_set_fused_argument_checks_and_memory():
     s = _solver("D3Q19", (64, 6, 4), vanse.FP32_SHIFTED, 2)
     base = s.device_bytes
-    for rows, planes in ((4, 1), (1, 0), (-1, 4), (16, 4)):  # 6 % 4, planes 0, negative, 16 rows
+    for rows, planes in ((7, 1), (1, 0), (-1, 4), (16, 4)):  # 7 > ny, planes 0, negative, 16 rows
         with pytest.raises(vanse.VanseError) as e:
             s.set_fused(rows, planes)
         assert e.value.code == vanse.EINVAL
@@ -137,7 +148,7 @@ def test_set_fused_argument_checks_and_memory():
     s.step(3)
     assert s.time == 7
     s.close()
-    for lat, dims in (("D3Q19", (96, 4, 4)), ("D2Q9", (64, 4, 1))):  # nx % 64, 2-D
+    for lat, dims in (("D3Q19", (600, 4, 4)), ("D2Q9", (64, 4, 1))):  # no shape, 2-D
         s = vanse.Solver(lat, dims, 0.7, vanse.FP32_SHIFTED)
         with pytest.raises(vanse.VanseError) as e:
             s.set_fused(2, 2)
