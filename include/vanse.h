@@ -154,7 +154,8 @@ enum {
     VANSE_TUNE_NONTEMPORAL = 1,
     VANSE_TUNE_XCD_REMAP = 2,
     VANSE_TUNE_FLAT = 4,
-    VANSE_TUNE_NT_STORES = 8
+    VANSE_TUNE_NT_STORES = 8,
+    VANSE_TUNE_TWO_STEP = 16   /* batches only: see vanse_batch_set_tuning */
 };
 int vanse_set_tuning(vanse_t h, int block, int flags);
 
@@ -189,20 +190,36 @@ int vanse_batch_destroy(vanse_batch_t b);
 /* Launch later work of b on stream (NULL = null stream). */
 int vanse_batch_set_stream(vanse_batch_t b, void *stream);
 
-/* Threads per block (64, 128, 256) and flags (VANSE_TUNE_NONTEMPORAL only)
- * of the batched kernel; chunk = steps per captured graph (0: no graph,
- * per-step launches).  Results do not depend on any of these. */
+/* Threads per block (64, 128, 256) and flags of the batched kernel; chunk =
+ * steps per captured graph (0: no graph, per-step launches).  Flags:
+ *   VANSE_TUNE_NONTEMPORAL  nontemporal population loads and stores
+ *   VANSE_TUNE_TWO_STEP     advance 3-D batches by the two-step launch (see
+ *       vanse_set_fused): each member gets general tiles (any size) of as
+ *       many x-rows as fit 512 interior and 1024 (FP64: 512) halo-plane cells
+ *       per block and segments of 32 planes, and a second population array
+ *       (allocated here, kept by the member's solver: its population memory
+ *       doubles).  Used for every group of 4 steps of a chunk while all
+ *       members sit at even time levels (two launches, so each member ends
+ *       the group in its first array); other steps, and batches whose members
+ *       do not fit such a tile (nx > 340; FP64 nx > 170; D3Q27 in FP64),
+ *       use the single-step batched launch.
+ * Results do not depend on any of these.  Errors: EINVAL, ENOMEM. */
 int vanse_batch_set_tuning(vanse_batch_t b, int block, int flags, int chunk);
 
 /* Advance every member n >= 0 steps (asynchronous).  Errors: EINVAL,
  * EUNSTABLE (a member is unstable), EDEVICE. */
 int vanse_batch_step(vanse_batch_t b, int64_t n);
 
-/* Autotune the batched launch shape: each candidate (block, flags) runs
- * `steps_per_trial` REAL steps of the batch, timed with HIP events, and the
- * fastest is kept and cached for batches of the same lattice, dtype and
- * size class.  Members advance 6 * steps_per_trial steps (0 if the choice
- * came from the cache; *steps_run tells).  Synchronises. */
+/* Autotune the batched launch shape: each candidate (block, flags: block
+ * 64/128/256 with and without VANSE_TUNE_NONTEMPORAL, and, for 3-D batches
+ * that fit it, VANSE_TUNE_TWO_STEP) runs `steps_per_trial` REAL steps of the
+ * batch, timed with HIP events (the two-step candidate on steps_per_trial
+ * rounded up to a multiple of 4, after one step to reach an even level if
+ * the members share an odd one), and the fastest per step is kept and cached
+ * for batches of the same lattice, dtype and size class.  Members advance
+ * the steps of every trial (0 if the choice came from the cache; *steps_run
+ * tells).  Second population arrays allocated for the two-step trial stay
+ * with the members.  Synchronises. */
 int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *flags,
                          int64_t *steps_run);
 

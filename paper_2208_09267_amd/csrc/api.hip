@@ -43,6 +43,16 @@ struct vanse_batch {
     hipGraphExec_t gexec = nullptr;
     hipStream_t stream = nullptr;
     std::string err;
+    // two-step launch (VANSE_TUNE_TWO_STEP)
+    bool two_step = false;              // requested
+    bool fused_ok = false;              // every member has a general tile
+    unsigned nblocks2 = 0;
+    size_t lds2 = 0;                    // LDS bytes per block of the two-step grid
+    vanse::BatchMember *d_members2 = nullptr;
+    unsigned *d_owner2 = nullptr;
+    size_t d_members2_cap = 0, cap_owner2 = 0;
+    std::vector<void *> layout_f2;      // members' second arrays in the two-step table
+    hipGraphExec_t gexec2 = nullptr;    // a full chunk of two-step launches
 };
 
 namespace vanse {
@@ -653,6 +663,9 @@ int bfail(vanse_batch *b, int code, const std::string &msg)
 void batch_free(vanse_batch *b)
 {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->gexec2) (void)hipGraphExecDestroy(b->gexec2);
+    (void)hipFree(b->d_members2);
+    (void)hipFree(b->d_owner2);
     for (int k = 0; k < 2; ++k) {
         if (b->tab_done[k]) (void)hipEventDestroy(b->tab_done[k]);
         if (b->h_tab[k]) (void)hipHostFree(b->h_tab[k]);
@@ -689,6 +702,85 @@ hipError_t batch_tables(vanse_batch *b)
         if (e == hipSuccess) e = hipEventRecord(b->tab_done[k], b->stream);
     }
     return e;
+}
+
+// Two-step tables: a general tile per member (batch_fused_rows x-rows,
+// segments of 32 planes), its second population array (allocated when
+// missing; the member's solver keeps it), and the owner table of that grid.
+// Leaves fused_ok false (single steps only) when a member has no tile.
+int batch_layout2(vanse_batch *b)
+{
+    b->fused_ok = false;
+    if (b->gexec2) {
+        (void)hipGraphExecDestroy(b->gexec2);
+        b->gexec2 = nullptr;
+    }
+    std::vector<vanse::BatchMember> mem(b->count);
+    std::vector<unsigned> owner;
+    unsigned begin = 0;
+    size_t lds = 0;
+    for (int k = 0; k < b->count; ++k) {
+        const Solver &s = b->members[k]->s;
+        const int rows = vanse::batch_fused_rows(s);
+        if (rows == 0) return VANSE_OK;
+        const int planes = std::min(32, s.geo.nz);
+        lds = std::max(lds, vanse::fused_lds_bytes(s.q, s.mode, s.geo.nx, rows));
+        const unsigned fnyb = (unsigned)((s.geo.ny + rows - 1) / rows);
+        const unsigned nzb = (unsigned)((s.geo.nz + planes - 1) / planes);
+        if ((size_t)begin + (size_t)fnyb * nzb > 0x7fffffffu) return VANSE_OK;
+        mem[k].block_begin = begin;
+        mem[k].nblocks = fnyb * nzb;
+        begin += mem[k].nblocks;
+    }
+    if (lds > (size_t)vanse::kFusedMaxLds) return VANSE_OK;
+    b->layout_f2.assign(b->count, nullptr);
+    for (int k = 0; k < b->count; ++k) {
+        Solver &s = b->members[k]->s;
+        if (!s.f_alt) {
+            hipError_t e = hipMalloc(&s.f_alt, s.f_bytes);
+            if (e != hipSuccess) {
+                s.f_alt = nullptr;
+                (void)hipGetLastError();
+                return bfail(b, VANSE_ENOMEM, std::string("vanse_batch: second population array: ") +
+                                                  hipGetErrorString(e));
+            }
+        }
+        const int rows = vanse::batch_fused_rows(s);
+        vanse::StepArgs a = vanse::step_args(s, s.t);
+        a.fty = (unsigned)rows;
+        a.fsz = (unsigned)std::min(32, s.geo.nz);
+        a.fnyb = (unsigned)((s.geo.ny + rows - 1) / rows);
+        a.fd_fnyb = vanse::make_fastdiv(a.fnyb);
+        a.f2 = s.f_alt;
+        mem[k].a = a;
+        owner.insert(owner.end(), mem[k].nblocks, (unsigned)k);
+        b->layout_f2[k] = s.f_alt;
+    }
+    hipError_t e;
+    if (!b->d_members2 || (size_t)b->count > b->d_members2_cap) {
+        (void)hipFree(b->d_members2);
+        b->d_members2 = nullptr;
+        b->d_members2_cap = (size_t)b->cap_count;
+        if ((e = hipMalloc((void **)&b->d_members2, sizeof(vanse::BatchMember) * b->d_members2_cap)) !=
+            hipSuccess)
+            return bfail(b, VANSE_ENOMEM, std::string("vanse_batch: hipMalloc: ") + hipGetErrorString(e));
+    }
+    if (!b->d_owner2 || owner.size() > b->cap_owner2) {
+        (void)hipFree(b->d_owner2);
+        b->d_owner2 = nullptr;
+        b->cap_owner2 = std::max(owner.size(), b->cap_owner2 + b->cap_owner2 / 2);
+        if ((e = hipMalloc((void **)&b->d_owner2, sizeof(unsigned) * b->cap_owner2)) != hipSuccess)
+            return bfail(b, VANSE_ENOMEM, std::string("vanse_batch: hipMalloc: ") + hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(b->d_members2, mem.data(), sizeof(vanse::BatchMember) * b->count,
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(b->d_owner2, owner.data(), sizeof(unsigned) * owner.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return bfail(b, VANSE_EDEVICE, std::string("vanse_batch: upload: ") + hipGetErrorString(e));
+    b->nblocks2 = begin;
+    b->lds2 = lds;
+    b->fused_ok = true;
+    return VANSE_OK;
 }
 
 // (Re)build the member and owner tables for the current block size.
@@ -740,7 +832,7 @@ int batch_layout(vanse_batch *b)
         (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
     }
-    return VANSE_OK;
+    return b->two_step ? batch_layout2(b) : VANSE_OK;
 }
 
 // Stage m(t_s + j) for j < k and t0 = t_s of every member and upload them.
@@ -773,23 +865,47 @@ hipError_t batch_launch(vanse_batch *b, int j, hipStream_t st)
                                     b->d_members, b->d_owner, mtab, t0, j, b->count, st);
 }
 
-// Capture `chunk` batched steps (j = 0 .. chunk-1) into an executable graph.
-int batch_capture(vanse_batch *b)
+hipError_t batch_launch2(vanse_batch *b, int j, int swap, hipStream_t st)
+{
+    const double *mtab = reinterpret_cast<const double *>(b->d_tab);
+    return vanse::launch_batch_fused(b->lattice, b->mode, b->nblocks2, b->lds2, b->d_members2,
+                                     b->d_owner2, mtab, j, b->count, swap, st);
+}
+
+// Steps 0 .. k-1 of a chunk: with `two`, each group of 4 steps is two
+// two-step launches (the second reads the members' second arrays and writes
+// back into the first); the remaining steps are single-step launches.
+hipError_t batch_chunk(vanse_batch *b, int k, bool two, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    int j = 0;
+    if (two)
+        for (; j + 4 <= k && e == hipSuccess; j += 4) {
+            e = batch_launch2(b, j, 0, st);
+            if (e == hipSuccess) e = batch_launch2(b, j + 2, 1, st);
+        }
+    for (; j < k && e == hipSuccess; ++j) e = batch_launch(b, j, st);
+    return e;
+}
+
+// Capture a full chunk (single-step or two-step form) into an executable graph.
+int batch_capture(vanse_batch *b, bool two)
 {
     hipStream_t cs = nullptr;
     hipGraph_t g = nullptr;
+    hipGraphExec_t *out = two ? &b->gexec2 : &b->gexec;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        for (int j = 0; j < b->chunk && e == hipSuccess; ++j) e = batch_launch(b, j, cs);
+        e = batch_chunk(b, b->chunk, two, cs);
         hipError_t e2 = hipStreamEndCapture(cs, &g);
         if (e == hipSuccess) e = e2;
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     if (cs) (void)hipStreamDestroy(cs);
     if (e != hipSuccess) {
-        b->gexec = nullptr;
+        *out = nullptr;
         return bfail(b, VANSE_EDEVICE, std::string("vanse_batch: graph capture: ") + hipGetErrorString(e));
     }
     return VANSE_OK;
@@ -802,8 +918,9 @@ int batch_run(vanse_batch *b, int64_t n, bool allow_graph)
         const Solver &s = b->members[k]->s;
         if (s.unstable) return bfail(b, VANSE_EUNSTABLE, "vanse_batch_step: a member is unstable");
         moved = moved || s.f != b->layout_f[k];
+        if (b->two_step && b->fused_ok) moved = moved || s.f_alt != b->layout_f2[k];
     }
-    if (moved) {  // a member switched population arrays (two-step launch) since the layout
+    if (moved) {  // a member switched or freed population arrays since the layout
         hipError_t e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) return bfail(b, VANSE_EDEVICE, std::string("vanse_batch_step: ") + hipGetErrorString(e));
         int rc = batch_layout(b);
@@ -811,14 +928,20 @@ int batch_run(vanse_batch *b, int64_t n, bool allow_graph)
     }
     while (n > 0) {
         const int k = (int)std::min<int64_t>(n, b->chunk_cap);
+        bool two = b->two_step && b->fused_ok && k >= 4;
+        for (int m = 0; m < b->count && two; ++m) two = (b->members[m]->s.t & 1) == 0;
         int rc = batch_upload(b, k);
         if (rc != VANSE_OK) return rc;
         hipError_t e = hipSuccess;
         if (allow_graph && b->chunk > 0 && k == b->chunk) {
-            if (!b->gexec && (rc = batch_capture(b)) != VANSE_OK) return rc;
-            e = hipGraphLaunch(b->gexec, b->stream);
+            hipGraphExec_t g = two ? b->gexec2 : b->gexec;
+            if (!g) {
+                if ((rc = batch_capture(b, two)) != VANSE_OK) return rc;
+                g = two ? b->gexec2 : b->gexec;
+            }
+            e = hipGraphLaunch(g, b->stream);
         } else {
-            for (int j = 0; j < k && e == hipSuccess; ++j) e = batch_launch(b, j, b->stream);
+            e = batch_chunk(b, k, two, b->stream);
         }
         if (e != hipSuccess)
             return bfail(b, VANSE_EDEVICE, std::string("vanse_batch_step: ") + hipGetErrorString(e));
@@ -919,18 +1042,22 @@ int vanse_batch_set_tuning(vanse_batch_t b, int block, int flags, int chunk)
     if (!b) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_set_tuning: NULL batch");
     if (block != 64 && block != 128 && block != 256)
         return bfail(b, VANSE_EINVAL, "vanse_batch_set_tuning: block must be 64, 128 or 256");
-    if (flags & ~VANSE_TUNE_NONTEMPORAL)
-        return bfail(b, VANSE_EINVAL, "vanse_batch_set_tuning: only VANSE_TUNE_NONTEMPORAL applies");
+    if (flags & ~(VANSE_TUNE_NONTEMPORAL | VANSE_TUNE_TWO_STEP))
+        return bfail(b, VANSE_EINVAL,
+                     "vanse_batch_set_tuning: only VANSE_TUNE_NONTEMPORAL and VANSE_TUNE_TWO_STEP apply");
     if (chunk < 0 || chunk > b->chunk_cap)
         return bfail(b, VANSE_EINVAL, "vanse_batch_set_tuning: chunk must be in [0, 16]");
-    const bool relayout = (block != b->block);
+    const bool two = (flags & VANSE_TUNE_TWO_STEP) != 0;
+    const bool relayout = (block != b->block) || (two && !b->two_step);
     b->block = block;
     b->nt = (flags & VANSE_TUNE_NONTEMPORAL) != 0;
+    b->two_step = two;
     b->chunk = chunk;
-    if (b->gexec) {
+    if (b->gexec || b->gexec2) {
         (void)hipStreamSynchronize(b->stream);
-        (void)hipGraphExecDestroy(b->gexec);
-        b->gexec = nullptr;
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        if (b->gexec2) (void)hipGraphExecDestroy(b->gexec2);
+        b->gexec = b->gexec2 = nullptr;
     }
     if (relayout) {
         (void)hipStreamSynchronize(b->stream);
@@ -991,6 +1118,32 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
                     best_flags = fl;
                 }
             }
+        // the two-step launch (3-D batches whose members all have a tile and
+        // share the parity of their time levels), timed on whole groups of 4
+        // steps and compared per step
+        if (rc == VANSE_OK && b->lattice != VANSE_D2Q9 &&
+            (rc = vanse_batch_set_tuning(b, best_block, best_flags | VANSE_TUNE_TWO_STEP,
+                                         b->chunk)) == VANSE_OK) {
+            bool same = b->fused_ok;
+            for (int m = 1; m < b->count && same; ++m)
+                same = ((b->members[m]->s.t ^ b->members[0]->s.t) & 1) == 0;
+            if (same && (b->members[0]->s.t & 1)) {  // align to an even level
+                rc = batch_run(b, 1, false);
+                run += 1;
+            }
+            const int trial = (steps_per_trial + 3) / 4 * 4;
+            if (same && rc == VANSE_OK) {
+                (void)hipEventRecord(e0, b->stream);
+                rc = batch_run(b, trial, false);
+                (void)hipEventRecord(e1, b->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                run += trial;
+                if (rc == VANSE_OK && ms / trial * steps_per_trial < best)
+                    best_flags |= VANSE_TUNE_TWO_STEP;
+            }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc != VANSE_OK) return rc;

@@ -157,6 +157,11 @@ hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, u
                              const BatchMember *members, const unsigned *owner,
                              const double *mtab, const long long *t0, int j, int count,
                              hipStream_t st);
+// Rows of a solve's general tile in the batched two-step launch (0: none).
+int batch_fused_rows(const Solver &s);
+hipError_t launch_batch_fused(int lattice, int mode, unsigned nblocks, size_t lds,
+                              const BatchMember *members, const unsigned *owner,
+                              const double *mtab, int j, int count, int swap, hipStream_t st);
 hipError_t launch_moments(const Solver &s, int parity, double m, double *rho, double *p,
                           double *u);
 hipError_t launch_populations(const Solver &s, int parity, double *f);

@@ -1180,6 +1180,53 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
     return rc;
 }
 
+int batch_fused_rows(const Solver &s)
+{
+    if (s.d != 3 || (long long)s.geo.ncells * 8 >= (1ll << 32)) return 0;
+    const int nx = s.geo.nx;
+    int rows;
+    if (s.mode == MODE_F64) {
+        if (s.lattice != 1) return 0;
+        rows = 512 / nx - 2;                            // 1 interior, 1 halo cell per thread
+    } else {
+        rows = std::min(512 / nx, 1024 / nx - 2);       // 1 interior, 2 halo cells per thread
+    }
+    rows = std::min(rows, s.geo.ny);
+    return rows >= 1 ? rows : 0;
+}
+
+hipError_t launch_batch_fused(int lattice, int mode, unsigned nblocks, size_t lds,
+                              const BatchMember *members, const unsigned *owner,
+                              const double *mtab, int j, int count, int swap, hipStream_t st)
+{
+    if (lattice == 0 || (mode == MODE_F64 && lattice != 1) || lds > (size_t)kFusedMaxLds)
+        return hipErrorInvalidValue;
+    return dispatch(lattice, mode, [&](auto lat, auto m) -> hipError_t {
+        using L = decltype(lat);
+        constexpr int M = decltype(m)::value;
+        if constexpr (L::D == 3 && !(M == MODE_F64 && L::Q != 19)) {
+            constexpr int H = M == MODE_F64 ? 1 : 2;
+            auto *fn = &batch_fused2_kernel<L, M, 1, H>;
+            static std::atomic<unsigned long long> raised{0};
+            int dev = 0;
+            hipError_t e = hipGetDevice(&dev);
+            if (e != hipSuccess) return e;
+            const unsigned long long bit = 1ull << (dev & 63);
+            if (lds > 65536 && !(raised.load() & bit)) {
+                if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             kFusedMaxLds)) != hipSuccess)
+                    return e;
+                raised.fetch_or(bit);
+            }
+            fn<<<nblocks, kFusedThreads, lds, st>>>(members, owner, mtab, j, count, swap);
+            return hipGetLastError();
+        } else {
+            return hipErrorInvalidValue;
+        }
+    });
+}
+
 hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, unsigned block,
                              const BatchMember *members, const unsigned *owner,
                              const double *mtab, const long long *t0, int j, int count,

@@ -41,7 +41,7 @@ EXPORTS = [
     "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
     "vanse_batch_last_error", "vanse_batch_update",
 ]
-TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT, TUNE_NT_STORES = 1, 2, 4, 8
+TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT, TUNE_NT_STORES, TUNE_TWO_STEP = 1, 2, 4, 8, 16
 
 
 class Launch(collections.namedtuple(

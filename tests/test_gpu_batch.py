@@ -57,8 +57,8 @@ def test_autotune_keeps_results_bitwise():
     members = [_make(d, t, s, dtype) for d, t, s in CASES]
     b = vanse.Batch(members)
     block, flags, run = b.autotune(2)
-    assert block in (64, 128, 256) and flags in (0, 1)
-    assert run in (0, 12)
+    assert block in (64, 128, 256) and flags in (0, 1, 16, 17)
+    assert run in (0, 16)  # 6 single-step trials of 2 steps, the two-step trial of 4
     b.step(20)
     for s in solo:
         s.step(run + 20)
@@ -110,4 +110,53 @@ def test_batch_update_changes_members_and_stays_bitwise():
         assert np.array_equal(s.populations().cpu().numpy(), m.populations().cpu().numpy())
     b.close()
     for s in solo + mem:
+        s.close()
+
+
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("steps,chunk", [(37, 16), (10, 0), (32, 16)])
+def test_two_step_batch_matches_solo_bitwise(dtype, steps, chunk):
+    """Members at even levels advance by two-step launches (general tiles for
+    every size; FP64 members wider than 170 cells keep single steps)."""
+    print("case", dtype, steps, chunk, flush=True)
+    pre = [0, 2, 0, 4, 2]
+    solo = [_make(d, t, s, dtype, p) for (d, t, s), p in zip(CASES, pre)]
+    for s in solo:
+        s.step(steps)
+    want = [s.populations().cpu().numpy() for s in solo]
+    for s in solo:
+        s.close()
+    members = [_make(d, t, s, dtype, p) for (d, t, s), p in zip(CASES, pre)]
+    b = vanse.Batch(members)
+    b.set_tuning(128, vanse.TUNE_TWO_STEP, chunk)
+    b.step(steps)
+    for k, s in enumerate(members):
+        assert s.time == pre[k] + steps
+        assert np.array_equal(s.populations().cpu().numpy(), want[k]), k
+    # the batch keeps going after a member stepped alone (two-step, odd count)
+    members[1].set_fused(1, 4)
+    members[1].step(3)
+    b.step(8)
+    ref = _make(*CASES[1], dtype, pre[1])
+    ref.step(steps + 3 + 8)
+    assert np.array_equal(members[1].populations().cpu().numpy(), ref.populations().cpu().numpy())
+    ref.close()
+    b.close()
+    for s in members:
+        s.close()
+
+
+def test_two_step_batch_mixed_parity_falls_back_to_single_steps():
+    dtype = vanse.FP32_SHIFTED
+    pre = [0, 1, 2, 3, 0]
+    solo = [_make(d, t, s, dtype, p) for (d, t, s), p in zip(CASES, pre)]
+    members = [_make(d, t, s, dtype, p) for (d, t, s), p in zip(CASES, pre)]
+    b = vanse.Batch(members)
+    b.set_tuning(256, vanse.TUNE_TWO_STEP, 16)
+    b.step(20)
+    for s, m in zip(solo, members):
+        s.step(20)
+        assert np.array_equal(s.populations().cpu().numpy(), m.populations().cpu().numpy())
+    b.close()
+    for s in solo + members:
         s.close()
