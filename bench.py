@@ -224,10 +224,13 @@ def batched_run(steps=500, trial=5):
     return {"workload": "64 D3Q19 solves, edges uniform in {32,48,64,96}, tau U[0.55,1.0], "
                         "seeded phi per solve, FP32 shifted, %d steps each" % steps,
             "total_cells": cells, "steps_timed": timed, "autotune_steps": run,
-            "launch": {"block": block, "nontemporal": bool(flags & 1), "graph_chunk": 16},
+            "launch": {"block": block, "nontemporal": bool(flags & 1),
+                       "two_step": bool(flags & vanse.TUNE_TWO_STEP), "graph_chunk": 16},
             "mlups": round(cells * timed / (ms / 1e3) / 1e6, 1),
-            "ms_per_step": round(ms / timed, 5), "gb_s": round(gbs, 1),
-            "frac_hbm": round(gbs / PEAK_HBM_GBS, 4)}
+            "ms_per_step": round(ms / timed, 5),
+            # bytes a one-step-per-pass kernel would move for the same throughput
+            "effective_gb_s_single_step_bytes": round(gbs, 1),
+            "effective_frac_single_step_bytes": round(gbs / PEAK_HBM_GBS, 4)}
 
 
 def _solve_fields(w, dtype, progress=None):

@@ -927,9 +927,12 @@ int batch_run(vanse_batch *b, int64_t n, bool allow_graph)
         if (rc != VANSE_OK) return rc;
     }
     while (n > 0) {
-        const int k = (int)std::min<int64_t>(n, b->chunk_cap);
+        int k = (int)std::min<int64_t>(n, b->chunk_cap);
         bool two = b->two_step && b->fused_ok && k >= 4;
+        bool odd = two;  // every member at an odd level: one single step re-aligns them
         for (int m = 0; m < b->count && two; ++m) two = (b->members[m]->s.t & 1) == 0;
+        for (int m = 0; m < b->count && odd; ++m) odd = (b->members[m]->s.t & 1) == 1;
+        if (odd && n >= 5) k = 1;
         int rc = batch_upload(b, k);
         if (rc != VANSE_OK) return rc;
         hipError_t e = hipSuccess;

@@ -33,13 +33,17 @@ _ELEM = {vanse.FP64: 8, vanse.FP32_SHIFTED: 4, vanse.FP16_SHIFTED: 2}
 _PERT = {vanse.FP64: 8, vanse.FP32_SHIFTED: 4, vanse.FP16_SHIFTED: 4}
 
 
-def state_bytes(lattice: str, dims, dtype: int) -> int:
+def state_bytes(lattice: str, dims, dtype: int, two_step: bool = False) -> int:
     """Device bytes one solve holds (the layout vanse_create allocates:
     Q population planes and one phi plane of stride round_up(ncells, 128),
-    plus the reduction scratch)."""
+    plus the reduction scratch; with two_step, on a 3-D lattice, the second
+    population array of the two-step launch)."""
     n = int(np.prod(dims))
     stride = (n + 127) // 128 * 128
-    return _Q[lattice] * stride * _ELEM[dtype] + stride * _PERT[dtype] + 8 * (7 * 1024 + 64)
+    pop = _Q[lattice] * stride * _ELEM[dtype]
+    if two_step and lattice != "D2Q9":
+        pop *= 2
+    return pop + stride * _PERT[dtype] + 8 * (7 * 1024 + 64)
 
 
 def admit_count(queue_bytes: Sequence[int], queue_cells: Sequence[int], used_bytes: int,
@@ -97,10 +101,14 @@ class _Active:
 class Server:
     """Continuous-batching loop.  budget_bytes: HBM the resident states may
     use; cell_cap: cells in flight; chunk: steps between admissions (and per
-    captured graph)."""
+    captured graph); two_step: let the batch use the two-step launch (its
+    second population arrays are counted in the budget; a request admitted
+    while the batch sits at an odd level takes one step alone first, so all
+    members share the parity the two-step launch needs)."""
 
     def __init__(self, budget_bytes=200e9, cell_cap=40_000_000, max_active=4096, chunk=16,
-                 dtype=vanse.FP32_SHIFTED, keep_fields=False, autotune=True, log=None):
+                 dtype=vanse.FP32_SHIFTED, keep_fields=False, autotune=True, log=None,
+                 two_step=True):
         self.budget = int(budget_bytes)
         self.cell_cap = int(cell_cap)
         self.max_active = int(max_active)
@@ -108,11 +116,15 @@ class Server:
         self.dtype = dtype
         self.keep_fields = keep_fields
         self.autotune = autotune
+        self.two_step = two_step
         self.log = log
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stats = collections.Counter()
         self.time = collections.Counter()  # host seconds per loop phase
-        self.tuning = (256, 0)
+        self.tuning = (256, vanse.TUNE_TWO_STEP if two_step else 0)
+
+    def _bytes(self, work: W.Workload) -> int:
+        return state_bytes(work.lattice, work.dims, self.dtype, self.two_step)
 
     def _start(self, rid, work: W.Workload, now) -> Tuple[Optional[_Active], Result]:
         res = Result(rid, work.name, arrival=now, steps=work.steps, cells=work.ncells)
@@ -152,7 +164,7 @@ class Server:
                 rid, (ta, work) = arrivals[i]
                 queue.append((rid, ta if realtime else 0.0, work))
                 i += 1
-            k = admit_count([state_bytes(w.lattice, w.dims, self.dtype) for _, _, w in queue],
+            k = admit_count([self._bytes(w) for _, _, w in queue],
                             [w.ncells for _, _, w in queue], used,
                             sum(a.work.ncells for a in active), len(active), self.budget,
                             self.cell_cap, self.max_active)
@@ -161,7 +173,7 @@ class Server:
                 rid, ta, work = queue.popleft()
                 res = Result(rid, work.name, ta, steps=work.steps, cells=work.ncells,
                              error="request needs %d bytes, over the HBM budget"
-                                   % state_bytes(work.lattice, work.dims, self.dtype))
+                                   % self._bytes(work))
                 res.finish = clock() - t0
                 results[rid] = res
                 continue
@@ -175,8 +187,11 @@ class Server:
                     results[rid] = res
                     self.stats["failed"] += 1
                     continue
+                if active and active[0].solver.time % 2 and act.remaining > 0:
+                    act.solver.step(1)  # join at the batch's parity
+                    act.remaining -= 1
                 active.append(act)
-                used += state_bytes(work.lattice, work.dims, self.dtype)
+                used += self._bytes(work)
                 dirty = True
             self.time["admit"] += clock() - tadm
             if not active:
@@ -192,12 +207,15 @@ class Server:
                 block, flags = self.tuning
                 if self.autotune:
                     # trial steps are real steps: keep them within every member's count
-                    trial = min(a.remaining for a in active) // 6
+                    # (6 single-step trials, a two-step trial of 4, one aligning step)
+                    trial = min(4, (min(a.remaining for a in active) - 5) // 6)
                     if trial >= 1:
                         block, flags, ran = batch.autotune(min(trial, 4))
                         self.tuning = (block, flags)
                         for a in active:
                             a.remaining -= ran
+                if not self.two_step:
+                    flags &= ~vanse.TUNE_TWO_STEP
                 batch.set_tuning(block, flags, self.chunk)
                 dirty = False
                 self.stats["rebuilds"] += 1
@@ -226,7 +244,7 @@ class Server:
                         torch.cuda.current_stream().synchronize()
                     a.result.finish = clock() - t0
                     results[a.rid] = a.result
-                    used -= state_bytes(a.work.lattice, a.work.dims, self.dtype)
+                    used -= self._bytes(a.work)
                     a.solver.close()
                     if self.log:
                         self.log(a.result)

@@ -23,13 +23,17 @@ def _requests():
     return out
 
 
+@pytest.mark.parametrize("autotune", [True, False])
 @pytest.mark.parametrize("dtype", [vanse.FP32_SHIFTED, vanse.FP64])
-def test_results_identical_alone_and_in_mix(dtype):
+def test_results_identical_alone_and_in_mix(dtype, autotune):
+    # mix: autotuned, or the two-step batched launch (requests joining at the
+    # batch's parity); alone: single steps only
     reqs = _requests()
-    mixed = serve.Server(dtype=dtype, keep_fields=True, chunk=16).run(reqs)
+    mixed = serve.Server(dtype=dtype, keep_fields=True, chunk=16, autotune=autotune).run(reqs)
     assert all(r.error is None for r in mixed)
     for (ta, w), got in zip(reqs, mixed):
-        alone = serve.Server(dtype=dtype, keep_fields=True, chunk=16, autotune=False).run([(0.0, w)])[0]
+        alone = serve.Server(dtype=dtype, keep_fields=True, chunk=16, autotune=False,
+                             two_step=False).run([(0.0, w)])[0]
         assert alone.error is None
         assert np.array_equal(alone.rho, got.rho), w.name
         assert np.array_equal(alone.p, got.p), w.name
@@ -58,7 +62,7 @@ def test_bad_request_fails_alone():
     good = [r for r in res if r.error is None]
     assert len(good) == 4
     for (ta, w), got in zip(reqs, good):
-        alone = serve.Server(keep_fields=True, autotune=False).run([(0.0, w)])[0]
+        alone = serve.Server(keep_fields=True, autotune=False, two_step=False).run([(0.0, w)])[0]
         assert np.array_equal(alone.u, got.u)
 
 
@@ -76,4 +80,6 @@ def test_state_bytes_matches_library(dtype):
     for dims in [(8, 8, 8), (33, 17, 5), (1, 1, 1)]:
         s = vanse.Solver("D3Q19", dims, 0.7, dtype)
         assert s.device_bytes == serve.state_bytes("D3Q19", dims, dtype)
+        s.set_fused(1, 4)  # the second population array of the two-step launch
+        assert s.device_bytes == serve.state_bytes("D3Q19", dims, dtype, two_step=True)
         s.close()

@@ -38,3 +38,7 @@ def test_state_bytes_formula(dtype, elem, pert):
     stride = (n + 127) // 128 * 128
     want = 19 * stride * elem + stride * pert + 8 * (7 * 1024 + 64)
     assert serve.state_bytes("D3Q19", (33, 17, 5), dtype) == want
+    # the two-step launch's second population array
+    assert serve.state_bytes("D3Q19", (33, 17, 5), dtype, two_step=True) == want + 19 * stride * elem
+    assert serve.state_bytes("D2Q9", (33, 17, 1), dtype, two_step=True) == \
+        serve.state_bytes("D2Q9", (33, 17, 1), dtype)
