@@ -38,9 +38,12 @@ DTYPE_NAME = {"fp64": "f64", "fp32_shifted": "f32", "fp16_shifted": "f32"}
 MODE_NAME = {"fp64": "FP64", "fp32_shifted": "FP32_SHIFTED", "fp16_shifted": "FP16_SHIFTED"}
 
 
-def kernel_name(variant, two_step, lattice="D3Q19"):
-    return "%s<%s, %s>" % ("fused2_kernel" if two_step else "step_kernel", lattice,
-                           MODE_NAME[variant])
+def kernel_name(variant, rows, lattice="D3Q19"):
+    """Label of the kernel a launch shape runs (two-step rows 0: single step);
+    the same labels key the committed counter record."""
+    from paper_2208_09267_amd.rocprof_summary import kernel_label
+    mode = {"fp64": 0, "fp32_shifted": 1, "fp16_shifted": 2}[variant]
+    return kernel_label("fused2_kernel" if rows else "step_kernel", lattice, mode, rows or None)
 
 
 def kernel_source_hash():
@@ -58,10 +61,8 @@ def measured_traffic(variant, kernel):
         rec = json.load(fh)
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    v = rec.get("variants", {}).get(variant)
-    if v is None or v.get("kernel") != kernel:
-        return None
-    return round(v.get("bytes_per_launch"))
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else round(k["bytes_per_launch"])
 
 
 # launch shapes the autotuner picks for this workload on MI355X (used with
@@ -133,7 +134,7 @@ def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
             "frac_hbm": gbs / PEAK_HBM_GBS, "bytes_per_launch": bytes_launch,
             "bytes_per_lup": BYTES_PER_PASS[variant] / per_launch,
             "effective_gb_s": eff, "effective_frac": eff / PEAK_HBM_GBS,
-            "kernel": kernel_name(variant, two_step), "mass": mass, "launch": launch,
+            "kernel": kernel_name(variant, fused[0]), "mass": mass, "launch": launch,
             "steps": steps}
 
 
@@ -174,8 +175,7 @@ def d3q27_run(steps=200, warmup=30):
         per_launch = 2 if L.fused_rows else 1
         gbs = bpl * w.ncells / (ms * per_launch / 1e3) / 1e9
         out[name] = {"mlups": round(w.ncells / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5),
-                     "kernel": "%s<D3Q27, %s>" % ("fused2_kernel" if L.fused_rows else "step_kernel",
-                                                  "FP64" if dt == vanse.FP64 else "FP32_SHIFTED"),
+                     "kernel": kernel_name(name, L.fused_rows, "D3Q27"),
                      "bytes_per_lup": bpl / per_launch, "gb_s": round(gbs, 1),
                      "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
                      "effective_frac_single_step_bytes":
@@ -426,6 +426,8 @@ def main():
                     help="skip the single-step comparison run of two-step variants")
     ap.add_argument("--fixed-launch", action="store_true",
                     help="use the recorded launch shapes instead of autotuning")
+    ap.add_argument("--fixed-shape", action="append", default=[],
+                    help="with --fixed-launch: VARIANT=tile_x,tile_y,flat,rows,planes")
     ap.add_argument("--precision", action="store_true",
                     help="run the FP32/FP16 error study instead of the throughput bench")
     ap.add_argument("--serve", action="store_true",
@@ -465,6 +467,9 @@ def main():
     pert_t = torch.from_numpy(pert).to(dev)
     u0_t = torch.from_numpy(np.ascontiguousarray(u0)).to(dev)
 
+    for spec in args.fixed_shape:
+        name, shape = spec.split("=")
+        FIXED_LAUNCH[name] = tuple(int(v) for v in shape.split(","))
     variants = [v for v in args.variants.split(",") if v]
     results = {}
     for v in variants:

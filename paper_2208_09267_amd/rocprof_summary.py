@@ -9,7 +9,7 @@ run.
 
 Usage (repository root):
   python -m paper_2208_09267_amd.rocprof_summary stats DIR
-  python -m paper_2208_09267_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR OUT_JSON
+  python -m paper_2208_09267_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR [FETCH_DIR WRITE_DIR ...] OUT_JSON
 """
 from __future__ import annotations
 
@@ -41,14 +41,28 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_label(kind: str, lattice: str, mode: int, rows=None) -> str:
+    """'step_kernel<D3Q19, FP32_SHIFTED>' or, for the two-step kernel with
+    tile rows, 'fused2_kernel<D3Q19, FP32_SHIFTED, rows 4>'."""
+    if kind == "fused2_kernel" and rows:
+        return "%s<%s, %s, rows %d>" % (kind, lattice, MODE_LABEL[mode], rows)
+    return "%s<%s, %s>" % (kind, lattice, MODE_LABEL[mode])
+
+
 def parse_name(full: str):
     """(label, lattice, mode) of a step kernel's demangled rocprofv3 name, or
-    None for other kernels.  label: 'fused2_kernel<D3Q19, FP32_SHIFTED>'."""
-    m = re.search(r"vanse::(fused2_kernel|step_kernel)<vanse::(D\dQ\d+), (\d)", full)
+    None for other kernels.  The two-step kernel's label carries its tile
+    rows when they are a compile-time argument."""
+    m = re.search(r"vanse::(fused2_kernel|step_kernel)<vanse::(D\dQ\d+), (\d)((?:, \w+)*)>", full)
     if not m:
         return None
     kind, lat, mode = m.group(1), m.group(2), int(m.group(3))
-    return "%s<%s, %s>" % (kind, lat, MODE_LABEL[mode]), lat, mode
+    rows = None
+    if kind == "fused2_kernel":
+        args = [a.strip() for a in m.group(4).split(",") if a.strip()]
+        if len(args) >= 4 and args[3].isdigit() and int(args[3]) > 0:
+            rows = int(args[3])
+    return kernel_label(kind, lat, mode, rows), lat, mode
 
 
 def _one(pattern):
@@ -67,8 +81,9 @@ def _counters(directory):
     return out
 
 
-def traffic(fetch_dir, write_dir):
-    fetch, write = _counters(fetch_dir), _counters(write_dir)
+def traffic(pairs):
+    """pairs: [(FETCH_SIZE run dir, WRITE_SIZE run dir), ...] of the same
+    kernels; each run is calibrated on its own copy kernel."""
 
     def calib(rows, name):
         vals = [v for k, vs in rows.items() if "copy_kernel" in k for v in vs]
@@ -77,26 +92,33 @@ def traffic(fetch_dir, write_dir):
         kib = sum(vals) / len(vals)
         return kib, COPY_BYTES / (kib * 1024.0)
 
-    f_kib, f_scale = calib(fetch, "FETCH_SIZE")
-    w_kib, w_scale = calib(write, "WRITE_SIZE")
     kernels = {}
-    for full in sorted(set(fetch) & set(write)):
-        p = parse_name(full)
-        if p is None:
-            continue
-        label, lat, mode = p
-        fb = sum(fetch[full]) / len(fetch[full]) * 1024.0 * f_scale
-        wb = sum(write[full]) / len(write[full]) * 1024.0 * w_scale
-        k = kernels.setdefault(label, {"rocprof_names": [], "dispatches": 0, "fetch_bytes": [],
-                                       "write_bytes": [], "mode": mode, "lattice": lat})
-        k["rocprof_names"].append(full)
-        k["dispatches"] += len(fetch[full])
-        k["fetch_bytes"].append(fb)
-        k["write_bytes"].append(wb)
+    calibration = []
+    for fetch_dir, write_dir in pairs:
+        fetch, write = _counters(fetch_dir), _counters(write_dir)
+        f_kib, f_scale = calib(fetch, "FETCH_SIZE")
+        w_kib, w_scale = calib(write, "WRITE_SIZE")
+        calibration.append({"copy_kernel_bytes": COPY_BYTES, "FETCH_SIZE_KiB": f_kib,
+                            "WRITE_SIZE_KiB": w_kib, "fetch_scale": f_scale,
+                            "write_scale": w_scale})
+        for full in sorted(set(fetch) & set(write)):
+            p = parse_name(full)
+            if p is None:
+                continue
+            label, lat, mode = p
+            fb = sum(fetch[full]) / len(fetch[full]) * 1024.0 * f_scale
+            wb = sum(write[full]) / len(write[full]) * 1024.0 * w_scale
+            k = kernels.setdefault(label, {"rocprof_names": [], "dispatches": 0, "fetch_bytes": [],
+                                           "write_bytes": [], "mode": mode, "lattice": lat})
+            if full not in k["rocprof_names"]:
+                k["rocprof_names"].append(full)
+            k["dispatches"] += len(fetch[full])
+            k["fetch_bytes"].append(fb)
+            k["write_bytes"].append(wb)
     for label, k in kernels.items():
         q = LATTICE_Q[k["lattice"]]
         mode = k["mode"]
-        k["fetch_bytes"] = sum(k["fetch_bytes"]) / len(k["fetch_bytes"])  # mean over parities
+        k["fetch_bytes"] = sum(k["fetch_bytes"]) / len(k["fetch_bytes"])  # mean over parities/runs
         k["write_bytes"] = sum(k["write_bytes"]) / len(k["write_bytes"])
         k["bytes_per_launch"] = k["fetch_bytes"] + k["write_bytes"]
         alg_read = (q * ELEM[mode] + PERT[mode]) * NCELLS_256
@@ -107,21 +129,11 @@ def traffic(fetch_dir, write_dir):
         k["fetch_ratio"] = k["fetch_bytes"] / alg_read
         k["write_ratio"] = k["write_bytes"] / alg_write
         k["ratio_to_algorithmic"] = k["bytes_per_launch"] / (alg_read + alg_write)
-    variants = {}
-    for label, k in kernels.items():
-        if k["lattice"] != "D3Q19":
-            continue
-        v = MODES[k["mode"]]
-        # the two-step kernel is the one the benchmark times when it exists
-        if v not in variants or label.startswith("fused2"):
-            variants[v] = {"kernel": label, "bytes_per_launch": k["bytes_per_launch"]}
     return {
         "kernel_source_hash": kernel_source_hash(),
         "workload": "D3Q19 256^3 (bench.py --fixed-launch)",
-        "calibration": {"copy_kernel_bytes": COPY_BYTES, "FETCH_SIZE_KiB": f_kib,
-                        "WRITE_SIZE_KiB": w_kib, "fetch_scale": f_scale, "write_scale": w_scale},
+        "calibration": calibration,
         "kernels": kernels,
-        "variants": variants,
     }
 
 
@@ -144,9 +156,9 @@ def main(argv):
         for r in stats(argv[1]):
             print("| `%s` | %d | %.1f | %.1f | %.1f |" % r)
         return 0
-    if len(argv) == 4 and argv[0] == "traffic":
-        rec = traffic(argv[1], argv[2])
-        with open(argv[3], "w") as fh:
+    if len(argv) >= 4 and len(argv) % 2 == 0 and argv[0] == "traffic":
+        rec = traffic(list(zip(argv[1:-1:2], argv[2:-1:2])))
+        with open(argv[-1], "w") as fh:
             json.dump(rec, fh, indent=1)
         for label, k in sorted(rec["kernels"].items()):
             print("%-40s fetch %.4g B (%.3f x)  write %.4g B (%.3f x)  per launch %.4g B (%.3f x)"
