@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__re
 // per lane, accesses use 32-bit element offsets, which the host allows only
 // when every array's byte size fits 32 bits) and a shorter last tile when fty
 // does not divide ny; otherwise nx is a multiple of 64 and fty divides ny.
-template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN>
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT>
 __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
 {
     static_assert(L::D == 3, "two-step launch: 3-D lattices only");
@@ -501,7 +501,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
     constexpr int Q = L::Q;
     // every thread owns one interior cell per IPT (no repeats): stores need no
     // trash slot
-    constexpr bool EXACT = !GEN && NXC > 0 && TYC > 0 && NXC * TYC == IPT * kFusedThreads;
+    constexpr bool EXACT = !GEN && NXC > 0 && TYC > 0 && NXC * TYC == IPT * NT;
     constexpr int RING = 5;                 // pert planes p-2 .. p+2
     constexpr int PPT = (5 * HPT + 2) / 3;  // pert values per thread and plane
     extern __shared__ __align__(16) unsigned char fused_lds[];
@@ -583,7 +583,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         const int pz = zmod(p);
         static_for<0, HPT>([&](auto hc) {
             constexpr int h = decltype(hc)::value;
-            const int idx = min(tid + h * kFusedThreads, HC - 1);
+            const int idx = min(tid + h * NT, HC - 1);
             const int hr = row_of(idx);
             const int x = idx - hr * nx;
             const int y = wrap(y0 + hr - 1, ny);
@@ -607,7 +607,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         const int qz = zmod(q);
         static_for<0, PPT>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            const int idx = min(tid + j * kFusedThreads, PC - 1);
+            const int idx = min(tid + j * NT, PC - 1);
             const int r = row_of(idx);
             const int x = idx - r * nx;
             const int y = ((y0 + r - 2) % ny + ny) % ny;
@@ -620,7 +620,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
     auto store_pert = [&](const R (&ph)[PPT], int s) {
         static_for<0, PPT>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            const int idx = min(tid + j * kFusedThreads, PC - 1);
+            const int idx = min(tid + j * NT, PC - 1);
             ring[s * PC + idx] = ph[j];  // repeats write the same value
         });
     };
@@ -655,7 +655,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         store_pert(ph, sp2);
         static_for<0, HPT>([&](auto hc) {
             constexpr int h = decltype(hc)::value;
-            const int idx = min(tid + h * kFusedThreads, HC - 1);
+            const int idx = min(tid + h * NT, HC - 1);
             const int hr = row_of(idx);
             const int x = idx - hr * nx;
             R v[Q];
@@ -683,8 +683,8 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         const int z = max(p - 1, z0);
         static_for<0, IPT>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const bool own = tid + k * kFusedThreads < NI && p > z0;  // wave-uniform unless GEN
-            const int cell = min(tid + k * kFusedThreads, NI - 1);
+            const bool own = tid + k * NT < NI && p > z0;  // wave-uniform unless GEN
+            const int cell = min(tid + k * NT, NI - 1);
             R t[Q];
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
@@ -751,11 +751,11 @@ __device__ __forceinline__ unsigned xcd_contiguous(unsigned b, unsigned n)
     return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
-// Two-step launch of one solve.
-template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN>
-__global__ void __launch_bounds__(kFusedThreads) fused2_kernel(StepArgs a)
+// Two-step launch of one solve, blocks of NT threads.
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT>
+__global__ void __launch_bounds__(NT) fused2_kernel(StepArgs a)
 {
-    fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN>(a, xcd_contiguous(blockIdx.x, gridDim.x));
+    fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN, NT>(a, xcd_contiguous(blockIdx.x, gridDim.x));
 }
 
 // Two-step launch of many solves (GEN tiles): block b belongs to solve
@@ -778,7 +778,7 @@ __global__ void __launch_bounds__(kFusedThreads)
         a.f = a.f2;
         a.f2 = t;
     }
-    fused2_tile<L, MODE, IPT, HPT, 0, 0, true>(a, b - members[s].block_begin);
+    fused2_tile<L, MODE, IPT, HPT, 0, 0, true, kFusedThreads>(a, b - members[s].block_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1106,8 +1106,9 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
     hipError_t rc = hipErrorInvalidValue;
     bool launched = false;
     const int nx = a.geo.nx, ty = (int)a.fty;
-    // one instantiation: IPT, HPT, (0 = runtime) compile-time nx / fty, GEN
-    auto go = [&](auto lat, auto mode, auto ic, auto hc, auto nxc, auto tyc, auto genc) {
+    // one instantiation: IPT, HPT, (0 = runtime) compile-time nx / fty, GEN, threads
+    auto go = [&](auto lat, auto mode, auto ic, auto hc, auto nxc, auto tyc, auto genc,
+                  auto ntc) {
         using L = decltype(lat);
         constexpr int M = decltype(mode)::value;
         constexpr int I = decltype(ic)::value;
@@ -1115,13 +1116,14 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
         constexpr int NXC = decltype(nxc)::value;
         constexpr int TYC = decltype(tyc)::value;
         constexpr bool GEN = decltype(genc)::value;
+        constexpr int NTC = decltype(ntc)::value;
         constexpr int LAT = std::is_same<L, D3Q19>::value ? 1 : 2;
         constexpr bool compiled =
             GEN ? (NXC == 0 && fused_compiled_gen(LAT, M, I, H)) : fused_compiled(LAT, M, I, H);
         if constexpr (compiled) {
-            if (launched || I != ipt || H != hpt || GEN != gen) return;
+            if (launched || GEN != gen || I != ipt || H != hpt) return;
             if (NXC && (NXC != nx || TYC != ty)) return;
-            auto *fn = &fused2_kernel<L, M, I, H, NXC, TYC, GEN>;
+            auto *fn = &fused2_kernel<L, M, I, H, NXC, TYC, GEN, NTC>;
             // slabs above 64 KiB need the kernel's LDS limit raised, once per device
             static std::atomic<unsigned long long> raised{0};
             int dev = 0;
@@ -1133,7 +1135,7 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
                 if (rc != hipSuccess) return;
                 raised.fetch_or(bit);
             }
-            fn<<<nblocks, kFusedThreads, lds, s.stream>>>(a);
+            fn<<<nblocks, NTC, lds, s.stream>>>(a);
             rc = hipGetLastError();
             launched = true;
         }
@@ -1151,24 +1153,25 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
         // 128-wide rows x 4 rows (D3Q19); 256-wide x 2 rows (D3Q27)
         using F = std::false_type;
         using G = std::true_type;
+        using N512 = std::integral_constant<int, kFusedThreads>;
         if constexpr (std::is_same<L, D3Q19>::value) {
-            go(lat, mode, C2{}, C3{}, C256{}, C4{}, F{});
-            go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{});
-            go(lat, mode, C1{}, C2{}, C128{}, C4{}, F{});
+            go(lat, mode, C2{}, C3{}, C256{}, C4{}, F{}, N512{});
+            go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{}, N512{});
+            go(lat, mode, C1{}, C2{}, C128{}, C4{}, F{}, N512{});
         } else {
-            go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{});
+            go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{}, N512{});
         }
-        go(lat, mode, C1{}, C1{}, C0{}, C0{}, F{});
-        go(lat, mode, C1{}, C2{}, C0{}, C0{}, F{});
-        go(lat, mode, C1{}, C3{}, C0{}, C0{}, F{});
-        go(lat, mode, C2{}, C2{}, C0{}, C0{}, F{});
-        go(lat, mode, C2{}, C3{}, C0{}, C0{}, F{});
-        go(lat, mode, C2{}, C4{}, C0{}, C0{}, F{});
-        go(lat, mode, C1{}, C1{}, C0{}, C0{}, G{});
-        go(lat, mode, C1{}, C2{}, C0{}, C0{}, G{});
-        go(lat, mode, C1{}, C3{}, C0{}, C0{}, G{});
-        go(lat, mode, C2{}, C2{}, C0{}, C0{}, G{});
-        go(lat, mode, C2{}, C3{}, C0{}, C0{}, G{});
+        go(lat, mode, C1{}, C1{}, C0{}, C0{}, F{}, N512{});
+        go(lat, mode, C1{}, C2{}, C0{}, C0{}, F{}, N512{});
+        go(lat, mode, C1{}, C3{}, C0{}, C0{}, F{}, N512{});
+        go(lat, mode, C2{}, C2{}, C0{}, C0{}, F{}, N512{});
+        go(lat, mode, C2{}, C3{}, C0{}, C0{}, F{}, N512{});
+        go(lat, mode, C2{}, C4{}, C0{}, C0{}, F{}, N512{});
+        go(lat, mode, C1{}, C1{}, C0{}, C0{}, G{}, N512{});
+        go(lat, mode, C1{}, C2{}, C0{}, C0{}, G{}, N512{});
+        go(lat, mode, C1{}, C3{}, C0{}, C0{}, G{}, N512{});
+        go(lat, mode, C2{}, C2{}, C0{}, C0{}, G{}, N512{});
+        go(lat, mode, C2{}, C3{}, C0{}, C0{}, G{}, N512{});
     };
     auto modes = [&](auto lat) {
         if (s.mode == MODE_F64) shapes(lat, std::integral_constant<int, MODE_F64>{});

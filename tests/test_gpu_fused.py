@@ -178,3 +178,4 @@ def test_batch_after_two_step_solo_steps_matches_single_steps():
     b.close()
     for m in mem:
         m.close()
+
