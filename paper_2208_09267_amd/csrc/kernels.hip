@@ -474,10 +474,10 @@ __global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__re
 //      pushed to x + xi_i of a.f2.
 // The perturbation pert (phi = eps_mean + m pert) of the rows y0-2 ..
 // y0+fty+1 is staged in an LDS ring of 5 planes (p-2 .. p+2), so the cell
-// updates read no global memory.  The populations of plane p + 1 and the
-// pert rows of plane p + 3 are loaded before step 4 of plane p: they are in
-// flight while the block computes, and no later global load waits behind
-// them.  nx is a multiple of 64, so every wave lies in one x-row: row bases
+// updates read no global memory.  Each halo cell's populations of plane p + 1
+// are loaded as soon as its values of plane p have been read, and the pert
+// rows of plane p + 3 before step 4 of plane p: they are in flight while the
+// block computes, and no later global load waits behind them.  nx is a multiple of 64, so every wave lies in one x-row: row bases
 // are scalar and a lane carries one 32-bit offset.  Per launch every
 // population is loaded (fty + 2)/fty (fsz + 2)/fsz times and stored once for
 // two lattice updates.  The cell arithmetic is the one of cell_step (phi_of,
@@ -579,28 +579,26 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         collide<L, MODE, R>(v, I, gx, gy, gz, R(a.omega), R(a.fcoef), Fex, Fey, Fez);
     };
     // natural-order populations of the fty + 2 rows of plane p
-    auto load_plane = [&](T (&raw)[HPT][Q], int p) {
+    // natural-order populations of halo cell h (of the fty + 2 rows) of plane p
+    auto load_cell = [&](T (&raw_h)[Q], int h, int p) {
         const int pz = zmod(p);
-        static_for<0, HPT>([&](auto hc) {
-            constexpr int h = decltype(hc)::value;
-            const int idx = min(tid + h * NT, HC - 1);
-            const int hr = row_of(idx);
-            const int x = idx - hr * nx;
-            const int y = wrap(y0 + hr - 1, ny);
-            if constexpr (GEN) {
-                const unsigned o = boff(pz * nxy + y * nx + x, sizeof(T));
-                static_for<0, Q>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    raw[h][i] = ld<T, false>(src + i * S, o);
-                });
-            } else {
-                const T *base = src + (pz * nxy + y * nx);
-                static_for<0, Q>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    raw[h][i] = ld<T, false>(base + i * S, (unsigned)x * (unsigned)sizeof(T));
-                });
-            }
-        });
+        const int idx = min(tid + h * NT, HC - 1);
+        const int hr = row_of(idx);
+        const int x = idx - hr * nx;
+        const int y = wrap(y0 + hr - 1, ny);
+        if constexpr (GEN) {
+            const unsigned o = boff(pz * nxy + y * nx + x, sizeof(T));
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                raw_h[i] = ld<T, false>(src + i * S, o);
+            });
+        } else {
+            const T *base = src + (pz * nxy + y * nx);
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                raw_h[i] = ld<T, false>(base + i * S, (unsigned)x * (unsigned)sizeof(T));
+            });
+        }
     };
     // pert of the PR ring rows of plane q: into registers, then into the ring
     auto load_pert = [&](R (&ph)[PPT], int q) {
@@ -641,7 +639,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         store_pert(ph, q - (z0 - 2));
     }
     load_pert(ph, z0 + 1);
-    load_plane(raw, z0 - 1);
+    static_for<0, HPT>([&](auto hc) { load_cell(raw[decltype(hc)::value], decltype(hc)::value, z0 - 1); });
     static_for<0, IPT * Q>([&](auto) { st<T, false>(trash, 0u, T(0)); });
 
     int s0 = 1;  // ring slot of plane p
@@ -663,6 +661,9 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
                 constexpr int i = decltype(ic)::value;
                 v[i] = St::decode(raw[h][i]);
             });
+            // the slot is free: its cell of plane p + 1 loads while this block
+            // computes the rest of plane p
+            load_cell(raw[h], h, p + 1);
             update(v, x, wrap(y0 + hr - 1, ny), hr + 1, ring_m1, ring_0, ring_p1, pz, R(a.m));
             // destination rows hr - 1 + cy of the slab and wrapped columns x + cx
             const int Ro[3] = {(hr - 2) * nx, (hr - 1) * nx, hr * nx};
@@ -676,7 +677,6 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         });
         __syncthreads();  // slab of plane p and ring plane p + 2 complete
         load_pert(ph, p + 3);
-        load_plane(raw, p + 1);
         // interior plane p - 1 is completed from p = z0 + 1 on; before that the
         // work is done on plane z0 (in range) and its results are discarded
         // (the ring slots it reads may not hold data yet)
@@ -751,9 +751,21 @@ __device__ __forceinline__ unsigned xcd_contiguous(unsigned b, unsigned n)
     return (xcd < r) ? xcd * (q + 1) + k : r * (q + 1) + (xcd - r) * q + k;
 }
 
+// Waves per SIMD the two-step kernel is compiled for: the compile-time D3Q19
+// FP32 tiles with one interior and at most two halo cells per thread are
+// held to 128 VGPRs (they fit without spilling) so that two 512-thread
+// blocks share a CU.
+template <class L, int MODE, int IPT, int HPT, int NXC, bool GEN, int NT>
+constexpr int fused_waves_per_simd()
+{
+    return (std::is_same<L, D3Q19>::value && MODE == MODE_F32S && !GEN && NXC > 0 &&
+            IPT == 1 && HPT <= 2 && NT == kFusedThreads) ? 4 : 1;
+}
+
 // Two-step launch of one solve, blocks of NT threads.
 template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT>
-__global__ void __launch_bounds__(NT) fused2_kernel(StepArgs a)
+__global__ void __launch_bounds__(NT, (fused_waves_per_simd<L, MODE, IPT, HPT, NXC, GEN, NT>()))
+    fused2_kernel(StepArgs a)
 {
     fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN, NT>(a, xcd_contiguous(blockIdx.x, gridDim.x));
 }
