@@ -97,7 +97,7 @@ def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
         ran = 0
     else:
         # warm-up: the autotuner's trial steps are real (untimed) steps
-        L = s.autotune(max(1, min(4, warmup // 12)) * 2)
+        L = s.autotune(8)  # real steps: they count as warm-up
         tile_x, tile_y, flags, ran = L.tile_x, L.tile_y, L.flags, L.steps_run
         fused = (L.fused_rows, L.fused_planes)
     two_step = fused[0] > 0
