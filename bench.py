@@ -185,19 +185,22 @@ def d3q27_run(steps=200, warmup=30):
     return out
 
 
-def batched_run(steps=500, trial=5):
-    """64 independent D3Q19 solves (edges 32/48/64/96, tau in [0.55, 1],
-    own seeded phi each), FP32 shifted, advanced together by the batched
-    launch; the launch shape comes from the autotuner, whose trial steps are
-    real steps and are included in the run.  Returns aggregate throughput of
-    the steps after tuning."""
+def batched_run(ws=None, steps=500, trial=5, workload=None):
+    """Independent D3Q19 solves, FP32 shifted, advanced together by the
+    batched launch (default: the 64 solves with edges 32/48/64/96, tau in
+    [0.55, 1], own seeded phi each); the launch shape comes from the
+    autotuner, whose trial steps are real steps and are included in the run.
+    Returns aggregate throughput of the steps after tuning."""
     import numpy as np
     import torch
 
     from paper_2208_09267_amd import vanse
     from paper_2208_09267_amd import workloads as W
 
-    ws = W.batched_64()
+    if ws is None:
+        ws = W.batched_64()
+        workload = ("64 D3Q19 solves, edges uniform in {32,48,64,96}, tau U[0.55,1.0], "
+                    "seeded phi per solve, FP32 shifted, %d steps each" % steps)
     dev = torch.device("cuda", 0)
     solvers = []
     for w in ws:
@@ -221,8 +224,7 @@ def batched_run(steps=500, trial=5):
     for s in solvers:
         s.close()
     gbs = BYTES_PER_PASS["fp32_shifted"] * cells * timed / (ms / 1e3) / 1e9
-    return {"workload": "64 D3Q19 solves, edges uniform in {32,48,64,96}, tau U[0.55,1.0], "
-                        "seeded phi per solve, FP32 shifted, %d steps each" % steps,
+    return {"workload": workload,
             "total_cells": cells, "steps_timed": timed, "autotune_steps": run,
             "launch": {"block": block, "nontemporal": bool(flags & 1),
                        "two_step": bool(flags & vanse.TUNE_TWO_STEP), "graph_chunk": 16},
@@ -231,6 +233,15 @@ def batched_run(steps=500, trial=5):
             # bytes a one-step-per-pass kernel would move for the same throughput
             "effective_gb_s_single_step_bytes": round(gbs, 1),
             "effective_frac_single_step_bytes": round(gbs / PEAK_HBM_GBS, 4)}
+
+
+def batched_256_run(count=4, steps=200):
+    """The batched launch at the headline size: `count` D3Q19 256^3 solves
+    (own tau and seeded phi each), FP32 shifted."""
+    from paper_2208_09267_amd import workloads as W
+    return batched_run(W.batched_256(count=count), steps=steps, trial=5,
+                       workload="%d D3Q19 256^3 solves, tau U[0.55,1.0], seeded phi per solve, "
+                                "FP32 shifted, %d steps each" % (count, steps))
 
 
 def _solve_fields(w, dtype, progress=None):
@@ -542,6 +553,8 @@ def main():
     if not args.no_batched:
         out["batched"] = batched_run()
         print("# batched: %s" % json.dumps(out["batched"]), file=sys.stderr, flush=True)
+        out["batched_256"] = batched_256_run()
+        print("# batched 256^3: %s" % json.dumps(out["batched_256"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, pert, u0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -170,6 +170,15 @@ def batched_64(seed=3, count=64):
     return out
 
 
+def batched_256(seed=5, count=4):
+    """`count` independent D3Q19 256^3 solves for the batched launch at the
+    headline size: tau uniform in [0.55, 1.0], phi seeded 2000 + s,
+    Taylor-Green amplitude 0.02, 200 steps each."""
+    rng = np.random.default_rng(seed)
+    return [Workload("batch256[%d]" % s, "D3Q19", (256, 256, 256), float(rng.uniform(0.55, 1.0)),
+                     200, 0.75, 1000.0, seed=2000 + s, tgv_amp=0.02) for s in range(count)]
+
+
 def served_arrivals(rate=20.0, duration=600.0, seed=4):
     """Poisson arrivals of D3Q19 requests: (arrival time, Workload).  Edge
     log-uniform in [32, 192], steps uniform in {500..5000}, tau uniform in
