@@ -109,18 +109,25 @@ __device__ __forceinline__ unsigned fdiv(unsigned n, const FastDiv &f)
 
 // Global memory access at a 32-bit byte offset from a base pointer.  With a
 // wave-uniform base the compiler emits the scalar-base (saddr) form, so a
-// lane carries one 32-bit offset instead of a 64-bit address.
+// lane carries one 32-bit offset instead of a 64-bit address.  The access
+// goes through a global address-space pointer: pointers that a batched
+// launch reads from its table in device memory carry no address space, and
+// the compiler would otherwise use flat instructions, which also count
+// against the LDS wait counter.
+template <class T>
+using global_t = __attribute__((address_space(1))) T;
 template <class T, bool NT>
 __device__ __forceinline__ T ld(const T *base, unsigned byte_off)
 {
-    const T *p = reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    const global_t<T> *p =
+        (const global_t<T> *)(reinterpret_cast<const char *>(base) + byte_off);
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
 template <class T, bool NT>
 __device__ __forceinline__ void st(T *base, unsigned byte_off, T v)
 {
-    T *p = reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off);
+    global_t<T> *p = (global_t<T> *)(reinterpret_cast<char *>(base) + byte_off);
     if constexpr (NT) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
@@ -664,16 +671,23 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
             // the slot is free: its cell of plane p + 1 loads while this block
             // computes the rest of plane p
             load_cell(raw[h], h, p + 1);
-            update(v, x, wrap(y0 + hr - 1, ny), hr + 1, ring_m1, ring_0, ring_p1, pz, R(a.m));
-            // destination rows hr - 1 + cy of the slab and wrapped columns x + cx
-            const int Ro[3] = {(hr - 2) * nx, (hr - 1) * nx, hr * nx};
-            const int Xd[3] = {(x == 0 ? nx : x) - 1, x, (x + 1 == nx) ? 0 : x + 1};
-            static_for<0, Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                const int r = hr - 1 + L::cy[i];
-                if ((unsigned)r < (unsigned)TY)  // wave-uniform unless GEN
-                    slab[i * NI + Ro[L::cy[i] + 1] + Xd[L::cx[i] + 1]] = St::encode(v[i]);
-            });
+            // a wave whose lanes all lie past the last halo cell only repeats
+            // that cell (another wave computes it): it keeps the loads, so
+            // every wave issues the same memory operations, and skips the
+            // collision and the pushes
+            constexpr bool FULL = !GEN && NXC > 0 && TYC > 0 && (h + 1) * NT <= (TYC + 2) * NXC;
+            if (FULL || (tid & ~63) + h * NT < HC) {
+                update(v, x, wrap(y0 + hr - 1, ny), hr + 1, ring_m1, ring_0, ring_p1, pz, R(a.m));
+                // destination rows hr - 1 + cy of the slab and wrapped columns x + cx
+                const int Ro[3] = {(hr - 2) * nx, (hr - 1) * nx, hr * nx};
+                const int Xd[3] = {(x == 0 ? nx : x) - 1, x, (x + 1 == nx) ? 0 : x + 1};
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    const int r = hr - 1 + L::cy[i];
+                    if ((unsigned)r < (unsigned)TY)  // wave-uniform unless GEN
+                        slab[i * NI + Ro[L::cy[i] + 1] + Xd[L::cx[i] + 1]] = St::encode(v[i]);
+                });
+            }
         });
         __syncthreads();  // slab of plane p and ring plane p + 2 complete
         load_pert(ph, p + 3);
