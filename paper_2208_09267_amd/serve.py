@@ -8,7 +8,10 @@ resident on the device, and advances ALL admitted solves together with the
 batched launch (one kernel per time step covering every solve; chunks of
 steps replay a captured graph).  A solve that reaches its step count is
 retired at the next chunk boundary: its moments are copied to the host and
-its memory is freed, which lets queued requests in.  Requests that arrive
+its memory is freed, which lets queued requests in.  While the head of the
+queue does not fit (or no request is left to arrive), nothing can join
+before the next retirement, so the batch runs straight to it without
+returning to the host between chunks.  Requests that arrive
 while others are on the GPU therefore overlap with them on the device.
 Because the per-cell arithmetic of the batched launch does not depend on
 the other members, every result is bitwise identical alone and in the mix.
@@ -152,6 +155,8 @@ class Server:
         clock = time.perf_counter
         t0 = clock()
         queue = collections.deque()  # (rid, arrival, workload)
+        queued_bytes = collections.deque()  # state bytes and cells of the queued requests
+        queued_cells = collections.deque()
         active: List[_Active] = []
         results = {}
         batch = None
@@ -160,26 +165,30 @@ class Server:
         used = 0
         while i < len(arrivals) or queue or active:
             now = clock() - t0
+            tadm = clock()
             while i < len(arrivals) and (not realtime or arrivals[i][1][0] <= now):
                 rid, (ta, work) = arrivals[i]
                 queue.append((rid, ta if realtime else 0.0, work))
+                queued_bytes.append(self._bytes(work))
+                queued_cells.append(work.ncells)
                 i += 1
-            k = admit_count([self._bytes(w) for _, _, w in queue],
-                            [w.ncells for _, _, w in queue], used,
-                            sum(a.work.ncells for a in active), len(active), self.budget,
-                            self.cell_cap, self.max_active)
+            k = admit_count(queued_bytes, queued_cells, used, sum(a.work.ncells for a in active),
+                            len(active), self.budget, self.cell_cap, self.max_active)
             if k == 0 and not active and queue:
                 # the head can never fit: fail it rather than wait forever
                 rid, ta, work = queue.popleft()
+                queued_bytes.popleft()
+                queued_cells.popleft()
                 res = Result(rid, work.name, ta, steps=work.steps, cells=work.ncells,
                              error="request needs %d bytes, over the HBM budget"
                                    % self._bytes(work))
                 res.finish = clock() - t0
                 results[rid] = res
                 continue
-            tadm = clock()
             for _ in range(k):
                 rid, ta, work = queue.popleft()
+                queued_bytes.popleft()
+                queued_cells.popleft()
                 act, res = self._start(rid, work, ta)
                 res.admit = clock() - t0
                 if act is None:
@@ -221,7 +230,14 @@ class Server:
                 self.stats["rebuilds"] += 1
                 self.time["rebuild"] += clock() - tr
             ts = clock()
-            step = min(self.chunk, min(a.remaining for a in active))
+            step = min(a.remaining for a in active)
+            if not queue and i < len(arrivals):
+                # room for requests still to arrive: stop at the next chunk
+                # boundary to admit them
+                step = min(step, self.chunk)
+            # otherwise nothing can join before the next retirement (the queue
+            # head does not fit, or no request is left to arrive): the batch
+            # runs to it without returning to the host between chunks
             if step > 0:
                 batch.step(step)
                 for a in active:
