@@ -73,6 +73,20 @@ def admit_count(queue_bytes: Sequence[int], queue_cells: Sequence[int], used_byt
     return k
 
 
+def steps_until_host(min_remaining: int, chunk: int, queue_waiting: bool,
+                     arrivals_left: bool) -> int:
+    """Steps the batch advances before the loop looks at the host again.
+
+    The first retirement comes after min_remaining steps.  While requests may
+    still arrive and nothing is queued, the loop stops at the next chunk
+    boundary so that a new arrival joins promptly.  Otherwise nothing can join
+    before that retirement (the queue head does not fit, or no request is left
+    to arrive), so the batch runs straight to it."""
+    if not queue_waiting and arrivals_left:
+        return min(min_remaining, chunk)
+    return min_remaining
+
+
 @dataclasses.dataclass
 class Result:
     rid: int
@@ -230,14 +244,8 @@ class Server:
                 self.stats["rebuilds"] += 1
                 self.time["rebuild"] += clock() - tr
             ts = clock()
-            step = min(a.remaining for a in active)
-            if not queue and i < len(arrivals):
-                # room for requests still to arrive: stop at the next chunk
-                # boundary to admit them
-                step = min(step, self.chunk)
-            # otherwise nothing can join before the next retirement (the queue
-            # head does not fit, or no request is left to arrive): the batch
-            # runs to it without returning to the host between chunks
+            step = steps_until_host(min(a.remaining for a in active), self.chunk, bool(queue),
+                                    i < len(arrivals))
             if step > 0:
                 batch.step(step)
                 for a in active:

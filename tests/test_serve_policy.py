@@ -1,5 +1,6 @@
 """CPU tests of the serving loop's host logic: the admission policy (a pure
-function of the budget and the queue) and the state-size formula."""
+function of the budget and the queue), how far the batch runs between host
+visits, and the state-size formula."""
 import pytest
 
 from paper_2208_09267_amd import serve, vanse
@@ -29,6 +30,17 @@ def test_idle_gpu_admits_one_oversized_request_but_never_over_budget():
     assert serve.admit_count([5, 5], [10_000, 1], 0, 0, 0, 10, 100, 64) == 1
     assert serve.admit_count([50], [1], 0, 0, 0, 10, 100, 64) == 0
     assert serve.admit_count([], [], 0, 0, 0, 10, 100, 64) == 0
+
+
+def test_steps_until_host():
+    # nothing queued, requests still to arrive: stop at the chunk boundary
+    assert serve.steps_until_host(500, 16, False, True) == 16
+    assert serve.steps_until_host(7, 16, False, True) == 7
+    # the queue head waits for memory: nothing joins before the next retirement
+    assert serve.steps_until_host(500, 16, True, True) == 500
+    # no request left to arrive: run to the next retirement
+    assert serve.steps_until_host(500, 16, False, False) == 500
+    assert serve.steps_until_host(3, 16, True, False) == 3
 
 
 @pytest.mark.parametrize("dtype,elem,pert", [(vanse.FP64, 8, 8), (vanse.FP32_SHIFTED, 4, 4),
