@@ -46,6 +46,7 @@ struct vanse_batch {
     // two-step launch (VANSE_TUNE_TWO_STEP)
     bool two_step = false;              // requested
     bool fused_ok = false;              // every member has a general tile
+    int uni_nx = 0, uni_rows = 0;       // the members' common compile-time tile (0: general tiles)
     unsigned nblocks2 = 0;
     size_t lds2 = 0;                    // LDS bytes per block of the two-step grid
     vanse::BatchMember *d_members2 = nullptr;
@@ -704,10 +705,13 @@ hipError_t batch_tables(vanse_batch *b)
     return e;
 }
 
-// Two-step tables: a general tile per member (batch_fused_rows x-rows,
-// segments of 32 planes), its second population array (allocated when
-// missing; the member's solver keeps it), and the owner table of that grid.
-// Leaves fused_ok false (single steps only) when a member has no tile.
+// Two-step tables: a tile per member, its second population array
+// (allocated when missing; the member's solver keeps it), and the owner table
+// of that grid.  When every member has the same nx and a compile-time tile of
+// that width divides its ny (batch_uniform_rows), all use that tile with
+// segments of 64 planes, as a single solve would; otherwise each member gets
+// a general tile (batch_fused_rows x-rows, segments of 32 planes).  Leaves
+// fused_ok false (single steps only) when a member has no tile.
 int batch_layout2(vanse_batch *b)
 {
     b->fused_ok = false;
@@ -715,15 +719,32 @@ int batch_layout2(vanse_batch *b)
         (void)hipGraphExecDestroy(b->gexec2);
         b->gexec2 = nullptr;
     }
+    int uni_nx = b->members[0]->s.geo.nx, uni_rows = 0;
+    for (int k = 0; k < b->count; ++k) {
+        const Solver &s = b->members[k]->s;
+        const int r = s.d == 3 && s.geo.nx == uni_nx
+                          ? vanse::batch_uniform_rows(b->lattice, b->mode, s.geo.nx, s.geo.ny)
+                          : 0;
+        if (r == 0 || (uni_rows && r != uni_rows)) {
+            uni_rows = 0;
+            break;
+        }
+        uni_rows = r;
+    }
+    if (uni_rows == 0) uni_nx = 0;
+    auto tile_rows = [&](const Solver &s) {
+        return uni_rows ? uni_rows : vanse::batch_fused_rows(s);
+    };
+    auto tile_planes = [&](const Solver &s) { return std::min(uni_rows ? 64 : 32, s.geo.nz); };
     std::vector<vanse::BatchMember> mem(b->count);
     std::vector<unsigned> owner;
     unsigned begin = 0;
     size_t lds = 0;
     for (int k = 0; k < b->count; ++k) {
         const Solver &s = b->members[k]->s;
-        const int rows = vanse::batch_fused_rows(s);
+        const int rows = tile_rows(s);
         if (rows == 0) return VANSE_OK;
-        const int planes = std::min(32, s.geo.nz);
+        const int planes = tile_planes(s);
         lds = std::max(lds, vanse::fused_lds_bytes(s.q, s.mode, s.geo.nx, rows));
         const unsigned fnyb = (unsigned)((s.geo.ny + rows - 1) / rows);
         const unsigned nzb = (unsigned)((s.geo.nz + planes - 1) / planes);
@@ -745,10 +766,10 @@ int batch_layout2(vanse_batch *b)
                                                   hipGetErrorString(e));
             }
         }
-        const int rows = vanse::batch_fused_rows(s);
+        const int rows = tile_rows(s);
         vanse::StepArgs a = vanse::step_args(s, s.t);
         a.fty = (unsigned)rows;
-        a.fsz = (unsigned)std::min(32, s.geo.nz);
+        a.fsz = (unsigned)tile_planes(s);
         a.fnyb = (unsigned)((s.geo.ny + rows - 1) / rows);
         a.fd_fnyb = vanse::make_fastdiv(a.fnyb);
         a.f2 = s.f_alt;
@@ -779,6 +800,8 @@ int batch_layout2(vanse_batch *b)
         return bfail(b, VANSE_EDEVICE, std::string("vanse_batch: upload: ") + hipGetErrorString(e));
     b->nblocks2 = begin;
     b->lds2 = lds;
+    b->uni_nx = uni_nx;
+    b->uni_rows = uni_rows;
     b->fused_ok = true;
     return VANSE_OK;
 }
@@ -868,8 +891,9 @@ hipError_t batch_launch(vanse_batch *b, int j, hipStream_t st)
 hipError_t batch_launch2(vanse_batch *b, int j, int swap, hipStream_t st)
 {
     const double *mtab = reinterpret_cast<const double *>(b->d_tab);
-    return vanse::launch_batch_fused(b->lattice, b->mode, b->nblocks2, b->lds2, b->d_members2,
-                                     b->d_owner2, mtab, j, b->count, swap, st);
+    return vanse::launch_batch_fused(b->lattice, b->mode, b->uni_nx, b->uni_rows, b->nblocks2,
+                                     b->lds2, b->d_members2, b->d_owner2, mtab, j, b->count, swap,
+                                     st);
 }
 
 // Steps 0 .. k-1 of a chunk: with `two`, each group of 4 steps is two

@@ -159,8 +159,14 @@ hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, u
                              hipStream_t st);
 // Rows of a solve's general tile in the batched two-step launch (0: none).
 int batch_fused_rows(const Solver &s);
-hipError_t launch_batch_fused(int lattice, int mode, unsigned nblocks, size_t lds,
-                              const BatchMember *members, const unsigned *owner,
+// Rows of the compile-time tile (nx a compile-time constant) that a batched
+// two-step launch uses when every member has this nx and a multiple of the
+// rows in y (0: none for this lattice, mode and size).
+int batch_uniform_rows(int lattice, int mode, int nx, int ny);
+// uni_nx, uni_rows: the members' common compile-time tile, or 0, 0 for
+// general tiles (each member's own rows).
+hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, unsigned nblocks,
+                              size_t lds, const BatchMember *members, const unsigned *owner,
                               const double *mtab, int j, int count, int swap, hipStream_t st);
 hipError_t launch_moments(const Solver &s, int parity, double m, double *rho, double *p,
                           double *u);

@@ -784,13 +784,16 @@ __global__ void __launch_bounds__(NT, (fused_waves_per_simd<L, MODE, IPT, HPT, N
     fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN, NT>(a, xcd_contiguous(blockIdx.x, gridDim.x));
 }
 
-// Two-step launch of many solves (GEN tiles): block b belongs to solve
-// owner[b] (after the XCD-contiguous order), whose tiles are a contiguous
-// range from members[s].block_begin.  Steps j and j + 1 of the chunk
-// (modulations mtab[j][s], mtab[j + 1][s]); swap: the solve's current
-// populations are in its second array (odd launch of a chunk).
-template <class L, int MODE, int IPT, int HPT>
-__global__ void __launch_bounds__(kFusedThreads)
+// Two-step launch of many solves: block b belongs to solve owner[b] (after
+// the XCD-contiguous order), whose tiles are a contiguous range from
+// members[s].block_begin.  Steps j and j + 1 of the chunk (modulations
+// mtab[j][s], mtab[j + 1][s]); swap: the solve's current populations are in
+// its second array (odd launch of a chunk).  GEN: general tiles, each member
+// with its own rows; otherwise every member has the compile-time tile NXC x
+// TYC of the single-solve launch.
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN>
+__global__ void __launch_bounds__(kFusedThreads,
+                                  (fused_waves_per_simd<L, MODE, IPT, HPT, NXC, GEN, kFusedThreads>()))
     batch_fused2_kernel(const BatchMember *__restrict__ members, const unsigned *__restrict__ owner,
                         const double *__restrict__ mtab, int j, int count, int swap)
 {
@@ -804,7 +807,7 @@ __global__ void __launch_bounds__(kFusedThreads)
         a.f = a.f2;
         a.f2 = t;
     }
-    fused2_tile<L, MODE, IPT, HPT, 0, 0, true, kFusedThreads>(a, b - members[s].block_begin);
+    fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN, kFusedThreads>(a, b - members[s].block_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1224,36 +1227,79 @@ int batch_fused_rows(const Solver &s)
     return rows >= 1 ? rows : 0;
 }
 
-hipError_t launch_batch_fused(int lattice, int mode, unsigned nblocks, size_t lds,
-                              const BatchMember *members, const unsigned *owner,
+int batch_uniform_rows(int lattice, int mode, int nx, int ny)
+{
+    int rows = 0;
+    if (lattice == 1 && nx == 256) rows = mode == MODE_F64 ? 2 : 4;
+    else if (lattice == 1 && nx == 128) rows = 4;
+    else if (lattice == 2 && nx == 256 && mode != MODE_F64) rows = 2;
+    if (rows == 4 && nx == 256 && ny % 4 != 0) rows = mode == MODE_F64 ? 0 : 2;
+    return (rows > 0 && ny % rows == 0) ? rows : 0;
+}
+
+hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, unsigned nblocks,
+                              size_t lds, const BatchMember *members, const unsigned *owner,
                               const double *mtab, int j, int count, int swap, hipStream_t st)
 {
-    if (lattice == 0 || (mode == MODE_F64 && lattice != 1) || lds > (size_t)kFusedMaxLds)
-        return hipErrorInvalidValue;
-    return dispatch(lattice, mode, [&](auto lat, auto m) -> hipError_t {
+    if (lattice == 0 || lds > (size_t)kFusedMaxLds) return hipErrorInvalidValue;
+    hipError_t rc = hipErrorInvalidValue;
+    bool launched = false;
+    // one instantiation: IPT, HPT, compile-time nx / rows (0, 0: general tiles)
+    auto go = [&](auto lat, auto m, auto ic, auto hc, auto nxc, auto tyc) {
         using L = decltype(lat);
         constexpr int M = decltype(m)::value;
-        if constexpr (L::D == 3 && !(M == MODE_F64 && L::Q != 19)) {
-            constexpr int H = M == MODE_F64 ? 1 : 2;
-            auto *fn = &batch_fused2_kernel<L, M, 1, H>;
+        constexpr int I = decltype(ic)::value;
+        constexpr int H = decltype(hc)::value;
+        constexpr int NXC = decltype(nxc)::value;
+        constexpr int TYC = decltype(tyc)::value;
+        constexpr bool GEN = NXC == 0;
+        constexpr int LAT = std::is_same<L, D3Q19>::value ? 1 : 2;
+        constexpr bool compiled =
+            GEN ? fused_compiled_gen(LAT, M, I, H) : fused_compiled(LAT, M, I, H);
+        if constexpr (compiled) {
+            if (launched || NXC != uni_nx || TYC != uni_rows) return;
+            auto *fn = &batch_fused2_kernel<L, M, I, H, NXC, TYC, GEN>;
             static std::atomic<unsigned long long> raised{0};
             int dev = 0;
-            hipError_t e = hipGetDevice(&dev);
-            if (e != hipSuccess) return e;
+            if ((rc = hipGetDevice(&dev)) != hipSuccess) return;
             const unsigned long long bit = 1ull << (dev & 63);
             if (lds > 65536 && !(raised.load() & bit)) {
-                if ((e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             kFusedMaxLds)) != hipSuccess)
-                    return e;
+                rc = hipFuncSetAttribute(reinterpret_cast<const void *>(fn),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, kFusedMaxLds);
+                if (rc != hipSuccess) return;
                 raised.fetch_or(bit);
             }
             fn<<<nblocks, kFusedThreads, lds, st>>>(members, owner, mtab, j, count, swap);
-            return hipGetLastError();
-        } else {
-            return hipErrorInvalidValue;
+            rc = hipGetLastError();
+            launched = true;
         }
+    };
+    (void)dispatch(lattice, mode, [&](auto lat, auto m) -> hipError_t {
+        using L = decltype(lat);
+        constexpr int M = decltype(m)::value;
+        using C0 = std::integral_constant<int, 0>;
+        using C1 = std::integral_constant<int, 1>;
+        using C2 = std::integral_constant<int, 2>;
+        using C3 = std::integral_constant<int, 3>;
+        using C4 = std::integral_constant<int, 4>;
+        using C128 = std::integral_constant<int, 128>;
+        using C256 = std::integral_constant<int, 256>;
+        if constexpr (L::D == 3) {
+            // general tiles: one interior and two halo cells per thread (FP64:
+            // one); the compile-time tiles of batch_uniform_rows
+            if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{});
+            else go(lat, m, C1{}, C2{}, C0{}, C0{});
+            if constexpr (std::is_same<L, D3Q19>::value) {
+                go(lat, m, C2{}, C3{}, C256{}, C4{});
+                go(lat, m, C1{}, C2{}, C256{}, C2{});
+                go(lat, m, C1{}, C2{}, C128{}, C4{});
+            } else {
+                go(lat, m, C1{}, C2{}, C256{}, C2{});
+            }
+        }
+        return hipSuccess;
     });
+    return launched ? rc : hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, unsigned block,

@@ -160,3 +160,51 @@ def test_two_step_batch_mixed_parity_falls_back_to_single_steps():
     b.close()
     for s in solo + members:
         s.close()
+
+
+# Members that share a compile-time tile of the single-solve launch (every
+# member as wide as the tile, its rows dividing ny) run the batched two-step
+# kernel with that tile; any other mix uses general tiles.
+TILE_GROUPS = {
+    "256x4": [((256, 8, 6), 0.6, 11), ((256, 4, 9), 0.8, 12), ((256, 12, 3), 1.1, 13)],
+    "256x2": [((256, 6, 5), 0.6, 14), ((256, 2, 3), 0.9, 15)],  # ny not a multiple of 4
+    "128x4": [((128, 8, 5), 0.7, 16), ((128, 4, 7), 0.95, 17)],
+    "mixed": [((256, 4, 4), 0.7, 18), ((128, 4, 5), 0.8, 19)],
+}
+
+
+def _make_lat(lat, dims, tau, seed, dtype, pre_steps=0):
+    pert = W.fourier_eps(dims, seed=seed)
+    s = vanse.Solver(lat, dims, tau, dtype)
+    s.set_porosity(0.75, torch.from_numpy(pert).cuda(), 40.0 + seed)
+    s.set_force((1e-6 * seed, -2e-7, 3e-7))
+    s.init(None, torch.from_numpy(np.ascontiguousarray(W.taylor_green(dims, 0.02))).cuda())
+    if pre_steps:
+        s.step(pre_steps)
+    return s
+
+
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("lat", ["D3Q19", "D3Q27"])
+@pytest.mark.parametrize("group", list(TILE_GROUPS))
+def test_two_step_batch_compile_time_tiles_bitwise(group, lat, dtype):
+    print("case", group, lat, dtype, flush=True)
+    cases = TILE_GROUPS[group]
+    pre = [0, 2, 4][:len(cases)]
+    steps = 37
+    solo = [_make_lat(lat, d, t, s, dtype, p) for (d, t, s), p in zip(cases, pre)]
+    for s in solo:
+        s.step(steps)
+    want = [s.populations().cpu().numpy() for s in solo]
+    for s in solo:
+        s.close()
+    members = [_make_lat(lat, d, t, s, dtype, p) for (d, t, s), p in zip(cases, pre)]
+    b = vanse.Batch(members)
+    b.set_tuning(256, vanse.TUNE_TWO_STEP, 16)
+    b.step(steps)
+    for k, s in enumerate(members):
+        assert s.time == pre[k] + steps
+        assert np.array_equal(s.populations().cpu().numpy(), want[k]), k
+    b.close()
+    for s in members:
+        s.close()
