@@ -194,9 +194,13 @@ int vanse_batch_set_stream(vanse_batch_t b, void *stream);
  * steps per captured graph (0: no graph, per-step launches).  Flags:
  *   VANSE_TUNE_NONTEMPORAL  nontemporal population loads and stores
  *   VANSE_TUNE_TWO_STEP     advance 3-D batches by the two-step launch (see
- *       vanse_set_fused): each member gets general tiles (any size) of as
- *       many x-rows as fit 512 interior and 1024 (FP64: 512) halo-plane cells
- *       per block and segments of 32 planes, and a second population array
+ *       vanse_set_fused): when every member has nx = 256 (rows: 4, or 2 in
+ *       FP64, in D3Q27, or when 4 does not divide ny) or nx = 128 (rows 4,
+ *       D3Q19) and those rows divide its ny, all use that compile-time tile
+ *       with segments of 64 planes, as a single solve would; otherwise each
+ *       member gets general tiles (any size) of as many x-rows as fit 512
+ *       interior and 1024 (FP64: 512) halo-plane cells per block and segments
+ *       of 32 planes.  Every member gets a second population array
  *       (allocated here, kept by the member's solver: its population memory
  *       doubles).  Used for every group of 4 steps of a chunk while all
  *       members sit at even time levels (two launches, so each member ends
