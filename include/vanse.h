@@ -195,8 +195,8 @@ int vanse_batch_set_stream(vanse_batch_t b, void *stream);
  *   VANSE_TUNE_NONTEMPORAL  nontemporal population loads and stores
  *   VANSE_TUNE_TWO_STEP     advance 3-D batches by the two-step launch (see
  *       vanse_set_fused): when every member has nx = 256 (rows: 4, or 2 in
- *       FP64, in D3Q27, or when 4 does not divide ny) or nx = 128 (rows 4,
- *       D3Q19) and those rows divide its ny, all use that compile-time tile
+ *       FP64 or when 4 does not divide ny) or nx = 128 (rows 4, D3Q19) and
+ *       those rows divide its ny, all use that compile-time tile
  *       with segments of 64 planes, as a single solve would; otherwise each
  *       member gets general tiles (any size) of as many x-rows as fit 512
  *       interior and 1024 (FP64: 512) halo-plane cells per block and segments
@@ -256,7 +256,8 @@ int vanse_set_tile(vanse_t h, int tile_x, int tile_y);
  * halo cells per thread, when nx is a multiple of 64 and rows divides ny
  *   D3Q19, FP32/FP16 storage: I <= 2 and H <= I + 2
  *   D3Q19, FP64: I = 1 and H <= 2
- *   D3Q27, FP32/FP16 storage: I = 1 and H <= 3, or I = 2 and H = 2
+ *   D3Q27, FP32/FP16 storage: I = 1 and H <= 3, or I = 2 and H = 2, or
+ *       nx = 256 with rows = 4
  *   D3Q27, FP64: none (single steps only);
  * otherwise (the general tile: any nx, a shorter last tile in y, and
  * nx * ny * nz * 8 < 2^32)

@@ -121,14 +121,26 @@ constexpr int kFusedThreads = 512;    // threads per block of the two-step launc
 constexpr int kFusedMaxLds = 160 * 1024;
 // Tile shapes of the two-step launch compiled into the library: ipt interior
 // and hpt halo-plane cells per thread, kept to the combinations whose
-// registers fit without spilling on gfx950.
-constexpr bool fused_compiled(int lattice, int mode, int ipt, int hpt)
+// registers fit without spilling on gfx950.  nxc: nx when the tile is one of
+// the compile-time tiles (fused_tile_nx), 0 for a runtime nx; D3Q27's
+// 256-wide 4-row tile fits only with nx and rows folded in.
+constexpr bool fused_compiled(int lattice, int mode, int ipt, int hpt, int nxc = 0)
 {
     if (lattice == 0 || ipt < 1 || hpt < ipt) return false;
     if (lattice == 2)  // D3Q27: 27 populations per cell in registers
-        return mode != MODE_F64 && (ipt == 1 ? hpt <= 3 : hpt <= 2);
+        return mode != MODE_F64 &&
+               (ipt == 1 ? hpt <= 3 : (hpt <= 2 || (nxc == 256 && hpt == 3)));
     if (mode == MODE_F64) return ipt == 1 && hpt <= 2;
     return ipt <= 2 && hpt <= ipt + 2;
+}
+// nx if (nx, rows) is a compile-time tile of the two-step launch (D3Q19:
+// 256 x 4, 256 x 2, 128 x 4; D3Q27: 256 x 4, 256 x 2), else 0.
+constexpr int fused_tile_nx(int lattice, int nx, int rows)
+{
+    if (lattice == 1)
+        return ((nx == 256 && (rows == 4 || rows == 2)) || (nx == 128 && rows == 4)) ? nx : 0;
+    if (lattice == 2) return (nx == 256 && (rows == 4 || rows == 2)) ? nx : 0;
+    return 0;
 }
 // The same for the general tile (any nx, shorter last tile), whose rows and
 // row bases are per lane.

@@ -1114,7 +1114,7 @@ bool fused_shape(int lattice, int mode, const Geometry &g, int rows, FusedShape 
         // 32-bit byte offsets: every population plane, pert and force array
         if ((long long)g.ncells * 8 >= (1ll << 32)) return false;
         if (!fused_compiled_gen(lattice, mode, sh.ipt, sh.hpt)) return false;
-    } else if (!fused_compiled(lattice, mode, sh.ipt, sh.hpt)) {
+    } else if (!fused_compiled(lattice, mode, sh.ipt, sh.hpt, fused_tile_nx(lattice, nx, rows))) {
         return false;
     }
     const int q = lattice == 0 ? 9 : (lattice == 1 ? 19 : 27);
@@ -1148,7 +1148,7 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
         constexpr int NTC = decltype(ntc)::value;
         constexpr int LAT = std::is_same<L, D3Q19>::value ? 1 : 2;
         constexpr bool compiled =
-            GEN ? (NXC == 0 && fused_compiled_gen(LAT, M, I, H)) : fused_compiled(LAT, M, I, H);
+            GEN ? (NXC == 0 && fused_compiled_gen(LAT, M, I, H)) : fused_compiled(LAT, M, I, H, NXC);
         if constexpr (compiled) {
             if (launched || GEN != gen || I != ipt || H != hpt) return;
             if (NXC && (NXC != nx || TYC != ty)) return;
@@ -1178,8 +1178,9 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
         using C4 = std::integral_constant<int, 4>;
         using C128 = std::integral_constant<int, 128>;
         using C256 = std::integral_constant<int, 256>;
-        // compiled shapes of the common tiles: 256-wide rows x 2 or 4 rows,
-        // 128-wide rows x 4 rows (D3Q19); 256-wide x 2 rows (D3Q27)
+        // compiled shapes of the common tiles (fused_tile_nx): 256-wide rows
+        // x 2 or 4 rows, 128-wide rows x 4 rows (D3Q19); 256-wide x 2 or 4
+        // rows (D3Q27)
         using F = std::false_type;
         using G = std::true_type;
         using N512 = std::integral_constant<int, kFusedThreads>;
@@ -1188,6 +1189,7 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
             go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{}, N512{});
             go(lat, mode, C1{}, C2{}, C128{}, C4{}, F{}, N512{});
         } else {
+            go(lat, mode, C2{}, C3{}, C256{}, C4{}, F{}, N512{});
             go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{}, N512{});
         }
         go(lat, mode, C1{}, C1{}, C0{}, C0{}, F{}, N512{});
@@ -1232,7 +1234,7 @@ int batch_uniform_rows(int lattice, int mode, int nx, int ny)
     int rows = 0;
     if (lattice == 1 && nx == 256) rows = mode == MODE_F64 ? 2 : 4;
     else if (lattice == 1 && nx == 128) rows = 4;
-    else if (lattice == 2 && nx == 256 && mode != MODE_F64) rows = 2;
+    else if (lattice == 2 && nx == 256 && mode != MODE_F64) rows = 4;
     if (rows == 4 && nx == 256 && ny % 4 != 0) rows = mode == MODE_F64 ? 0 : 2;
     return (rows > 0 && ny % rows == 0) ? rows : 0;
 }
@@ -1255,7 +1257,7 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, u
         constexpr bool GEN = NXC == 0;
         constexpr int LAT = std::is_same<L, D3Q19>::value ? 1 : 2;
         constexpr bool compiled =
-            GEN ? fused_compiled_gen(LAT, M, I, H) : fused_compiled(LAT, M, I, H);
+            GEN ? fused_compiled_gen(LAT, M, I, H) : fused_compiled(LAT, M, I, H, NXC);
         if constexpr (compiled) {
             if (launched || NXC != uni_nx || TYC != uni_rows) return;
             auto *fn = &batch_fused2_kernel<L, M, I, H, NXC, TYC, GEN>;
@@ -1294,6 +1296,7 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, u
                 go(lat, m, C1{}, C2{}, C256{}, C2{});
                 go(lat, m, C1{}, C2{}, C128{}, C4{});
             } else {
+                go(lat, m, C2{}, C3{}, C256{}, C4{});
                 go(lat, m, C1{}, C2{}, C256{}, C2{});
             }
         }

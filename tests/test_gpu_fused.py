@@ -30,7 +30,8 @@ def _compiled(lat, dtype, dims, rows):
         return False
     if nx % 64 == 0 and ny % rows == 0:
         if lat == "D3Q27":
-            return dtype != vanse.FP64 and (h <= 3 if i == 1 else (i == 2 and h == 2))
+            return dtype != vanse.FP64 and (h <= 3 if i == 1 else
+                                            (i == 2 and (h == 2 or (nx == 256 and rows == 4))))
         if dtype == vanse.FP64:
             return i == 1 and h <= 2
         return i <= 2 and h <= i + 2
@@ -82,7 +83,7 @@ SHAPES = [("D3Q19", (64, 8, 6), 1, 4), ("D3Q19", (64, 8, 6), 2, 32), ("D3Q19", (
           ("D3Q19", (64, 1, 2), 1, 1), ("D3Q19", (192, 6, 7), 3, 5), ("D3Q19", (256, 4, 9), 4, 4),
           ("D3Q19", (128, 12, 3), 6, 2),
           ("D3Q27", (64, 4, 5), 2, 2), ("D3Q27", (64, 8, 6), 8, 4), ("D3Q27", (128, 6, 4), 3, 3),
-          ("D3Q27", (64, 3, 1), 3, 1),
+          ("D3Q27", (64, 3, 1), 3, 1), ("D3Q27", (256, 4, 5), 4, 3), ("D3Q27", (256, 8, 3), 4, 2),
           # general tiles: nx not a multiple of 64, rows not dividing ny (shorter last tile)
           ("D3Q19", (48, 10, 7), 4, 3), ("D3Q19", (33, 17, 5), 5, 2), ("D3Q19", (96, 7, 6), 3, 4),
           ("D3Q19", (7, 5, 3), 2, 1), ("D3Q19", (1, 1, 1), 1, 1), ("D3Q19", (64, 9, 4), 4, 8),
