@@ -370,6 +370,8 @@ def serve_run(rate, duration, budget, cell_cap, seed=4):
                 "offered_glups": offered / 1e9, "hbm_budget_gb": budget / 1e9,
                 "cell_cap": cell_cap, "batch_rebuilds": srv.stats["rebuilds"],
                 "chunks": srv.stats["chunks"],
+                "batch_steps_by_tuning": {"two_step": srv.stats["steps_two_step_tuning"],
+                                          "single_step": srv.stats["steps_single_step_tuning"]},
                 "loop_seconds": {k: round(v, 2) for k, v in srv.time.items()}})
     return out
 

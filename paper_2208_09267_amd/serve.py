@@ -251,6 +251,9 @@ class Server:
                 for a in active:
                     a.remaining -= step
                 self.stats["chunks"] += 1
+                # batch steps taken under a two-step or a single-step tuning
+                two = self.two_step and self.tuning[1] & vanse.TUNE_TWO_STEP
+                self.stats["steps_two_step_tuning" if two else "steps_single_step_tuning"] += step
             torch.cuda.current_stream().synchronize()
             self.time["step"] += clock() - ts
             done = [a for a in active if a.remaining <= 0]
