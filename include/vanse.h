@@ -217,10 +217,13 @@ int vanse_batch_step(vanse_batch_t b, int64_t n);
 /* Autotune the batched launch shape: each candidate (block, flags: block
  * 64/128/256 with and without VANSE_TUNE_NONTEMPORAL, and, for 3-D batches
  * that fit it, VANSE_TUNE_TWO_STEP) runs `steps_per_trial` REAL steps of the
- * batch, timed with HIP events (the two-step candidate on steps_per_trial
- * rounded up to a multiple of 4, after one step to reach an even level if
- * the members share an odd one), and the fastest per step is kept and cached
- * for batches of the same lattice, dtype and size class.  Members advance
+ * batch, timed with HIP events; then the two-step candidate (on
+ * steps_per_trial rounded up to a multiple of 4, after one step to reach an
+ * even level if the members share an odd one) and the best single-step
+ * candidate (steps_per_trial rounded up to even) each run twice in a row,
+ * the faster run of each counting; the fastest per step is kept and cached for batches of the same
+ * lattice, dtype and size class (not cached when the members' time levels
+ * differ in parity, which leaves the two-step candidate untried).  Members advance
  * the steps of every trial (0 if the choice came from the cache; *steps_run
  * tells).  Second population arrays allocated for the two-step trial stay
  * with the members.  Synchronises. */

@@ -1123,6 +1123,7 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
         }
     }
     if (!cached) {
+        bool cache = true;
         const int blocks[3] = {64, 128, 256};
         float best = 1e30f;
         hipEvent_t e0, e1;
@@ -1146,8 +1147,10 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
                 }
             }
         // the two-step launch (3-D batches whose members all have a tile and
-        // share the parity of their time levels), timed on whole groups of 4
-        // steps and compared per step
+        // share the parity of their time levels) against the best single-step
+        // candidate, re-timed here: the sweep above took the fastest of six
+        // noisy samples, each run after a different candidate, so comparing
+        // one two-step sample with it would bias the choice
         if (rc == VANSE_OK && b->lattice != VANSE_D2Q9 &&
             (rc = vanse_batch_set_tuning(b, best_block, best_flags | VANSE_TUNE_TWO_STEP,
                                          b->chunk)) == VANSE_OK) {
@@ -1158,24 +1161,43 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
                 rc = batch_run(b, 1, false);
                 run += 1;
             }
-            const int trial = (steps_per_trial + 3) / 4 * 4;
-            if (same && rc == VANSE_OK) {
+            // whole groups of 4 steps for the two-step launch, an even count
+            // for the single-step one (so the members stay at even levels)
+            const int t2 = (steps_per_trial + 3) / 4 * 4, t1 = (steps_per_trial + 1) / 2 * 2;
+            auto timed = [&](int n, float *per_step) {
                 (void)hipEventRecord(e0, b->stream);
-                rc = batch_run(b, trial, false);
+                rc = batch_run(b, n, false);
                 (void)hipEventRecord(e1, b->stream);
                 (void)hipEventSynchronize(e1);
                 float ms = 0.f;
                 (void)hipEventElapsedTime(&ms, e0, e1);
-                run += trial;
-                if (rc == VANSE_OK && ms / trial * steps_per_trial < best)
-                    best_flags |= VANSE_TUNE_TWO_STEP;
-            }
+                run += n;
+                *per_step = std::min(*per_step, ms / n);
+            };
+            // both table sets stay valid, so the runs switch the path with
+            // the flag alone (a table rebuild between them would leave the
+            // GPU idle and the next run starting slow)
+            // Each path runs twice in a row and the faster run counts: the
+            // first run after the other path starts from that path's cache
+            // state (which array was written last), the second from its own.
+            float two = 1e30f, one = 1e30f;
+            b->two_step = true;
+            for (int rep = 0; rep < 2 && same && rc == VANSE_OK; ++rep) timed(t2, &two);
+            b->two_step = false;
+            for (int rep = 0; rep < 2 && same && rc == VANSE_OK; ++rep) timed(t1, &one);
+            b->two_step = true;
+            if (rc == VANSE_OK && same && two < one) best_flags |= VANSE_TUNE_TWO_STEP;
+            // members at different parities could not try the two-step
+            // launch: leave the size class uncached so that a later call can
+            if (!same) cache = false;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc != VANSE_OK) return rc;
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = {best_block, best_flags};
+        if (cache) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = {best_block, best_flags};
+        }
     }
     int rc = vanse_batch_set_tuning(b, best_block, best_flags, b->chunk);
     if (rc != VANSE_OK) return rc;

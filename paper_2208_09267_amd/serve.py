@@ -138,7 +138,9 @@ class Server:
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stats = collections.Counter()
         self.time = collections.Counter()  # host seconds per loop phase
+        # default batched launch, and the autotuned one per size class
         self.tuning = (256, vanse.TUNE_TWO_STEP if two_step else 0)
+        self._tuned = {}
 
     def _bytes(self, work: W.Workload) -> int:
         return state_bytes(work.lattice, work.dims, self.dtype, self.two_step)
@@ -175,6 +177,7 @@ class Server:
         results = {}
         batch = None
         dirty = False
+        block, flags = self.tuning  # the batched launch in effect
         i = 0
         used = 0
         while i < len(arrivals) or queue or active:
@@ -229,12 +232,19 @@ class Server:
                     batch.update([a.solver for a in active])
                 block, flags = self.tuning
                 if self.autotune:
+                    # the library caches its choice per size class (log2 of the
+                    # cells); a class without a choice yet is tuned when the
+                    # trials fit, otherwise it takes the default launch
+                    cls = sum(a.work.ncells for a in active).bit_length() - 1
+                    block, flags = self._tuned.get(cls, self.tuning)
                     # trial steps are real steps: keep them within every member's count
-                    # (6 single-step trials, a two-step trial of 4, one aligning step)
-                    trial = min(4, (min(a.remaining for a in active) - 5) // 6)
-                    if trial >= 1:
-                        block, flags, ran = batch.autotune(min(trial, 4))
-                        self.tuning = (block, flags)
+                    # (6 single-step trials of t, one aligning step, then twice a
+                    # two-step trial of 4 and a single-step one of t rounded up to
+                    # even: at most 8 t + 11 steps for t <= 4)
+                    trial = min(4, (min(a.remaining for a in active) - 11) // 8)
+                    if cls not in self._tuned and trial >= 1:
+                        block, flags, ran = batch.autotune(trial)
+                        self._tuned[cls] = (block, flags)
                         for a in active:
                             a.remaining -= ran
                 if not self.two_step:
@@ -252,7 +262,7 @@ class Server:
                     a.remaining -= step
                 self.stats["chunks"] += 1
                 # batch steps taken under a two-step or a single-step tuning
-                two = self.two_step and self.tuning[1] & vanse.TUNE_TWO_STEP
+                two = self.two_step and flags & vanse.TUNE_TWO_STEP
                 self.stats["steps_two_step_tuning" if two else "steps_single_step_tuning"] += step
             torch.cuda.current_stream().synchronize()
             self.time["step"] += clock() - ts

@@ -58,7 +58,9 @@ def test_autotune_keeps_results_bitwise():
     b = vanse.Batch(members)
     block, flags, run = b.autotune(2)
     assert block in (64, 128, 256) and flags in (0, 1, 16, 17)
-    assert run in (0, 16)  # 6 single-step trials of 2 steps, the two-step trial of 4
+    # 6 single-step trials of 2 steps, then twice a two-step trial of 4 and the
+    # best single-step candidate on 2
+    assert run in (0, 24)
     b.step(20)
     for s in solo:
         s.step(run + 20)
@@ -144,6 +146,28 @@ def test_two_step_batch_matches_solo_bitwise(dtype, steps, chunk):
     b.close()
     for s in members:
         s.close()
+
+
+def test_autotune_does_not_cache_an_untried_two_step_launch():
+    dtype = vanse.FP16_SHIFTED  # D3Q27 in FP16: a tuning-cache key no other test uses
+    pre = [0, 1, 0, 1, 0]
+    members = [_make_lat("D3Q27", d, t, s, dtype, p) for (d, t, s), p in zip(CASES, pre)]
+    b = vanse.Batch(members)
+    block, flags, run = b.autotune(1)
+    assert run == 6 and not flags & vanse.TUNE_TWO_STEP  # mixed parity: single steps only
+    b.close()
+    for m in members:
+        if m.time % 2:
+            m.step(1)
+    b = vanse.Batch(members)
+    block, flags, run = b.autotune(1)
+    assert run == 6 + 2 * (4 + 2)  # not cached: the two-step candidate is tried now
+    b.close()
+    b = vanse.Batch(members)
+    assert b.autotune(1) == (block, flags, 0)
+    b.close()
+    for m in members:
+        m.close()
 
 
 def test_two_step_batch_mixed_parity_falls_back_to_single_steps():
