@@ -1,0 +1,188 @@
+"""Host emulation of the two-step kernel's indexing (CPU).
+
+The two-step launch (two time levels per launch through an LDS tile that
+marches in z) is only correct if every index it computes stays in bounds and
+its staging buffers hold the right data when read.  This test walks every
+block, loop iteration and thread of the tile scheme for many lattice shapes
+and tile sizes -- general tiles (any nx, a shorter last tile in y) and the
+compile-time ones -- and checks, as the kernel computes them:
+
+* global population, phi and output addresses lie inside their arrays;
+* the LDS slab: each interior cell of the tile receives each direction from
+  exactly one halo cell per plane (the repeated lanes past the last halo cell
+  aside), at an index inside the slab;
+* the LDS phi ring of 5 planes: every read finds the plane it wants in its
+  slot, written before the barrier that precedes the read;
+* each destination slot of the output array is written by exactly one owning
+  thread over the launch.
+
+The emulation restates the kernel's index arithmetic in numpy; it shares no
+code with the HIP source.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+NT = 512
+D3Q19 = [(0,0,0),(1,0,0),(0,1,0),(0,0,1),(1,1,0),(1,-1,0),(1,0,1),(1,0,-1),(0,1,1),(0,1,-1),
+         (-1,0,0),(0,-1,0),(0,0,-1),(-1,-1,0),(-1,1,0),(-1,0,-1),(-1,0,1),(0,-1,-1),(0,-1,1)]
+D3Q27 = [(0,0,0)] + [c for c in itertools.product((-1,0,1), repeat=3) if c != (0,0,0) and c > (0,0,0)]
+D3Q27 = D3Q27 + [tuple(-v for v in c) for c in D3Q27[1:]]
+
+
+def check(nx, ny, nz, TY, SZ, lat, full=True):
+    Q = len(lat)
+    ncells = nx * ny * nz
+    S = (ncells + 127) // 128 * 128
+    nxy = nx * ny
+    TYMAX = TY
+    IPT, HPT = -(-nx * TY // NT), -(-nx * (TY + 2) // NT)
+    PPT = (5 * HPT + 2) // 3
+    fnyb = -(-ny // TY)
+    nzb = -(-nz // SZ)
+    tid = np.arange(NT)
+    written = np.zeros((Q, ncells), np.int32)
+
+    def wrap(v, n):
+        r = np.where(v < 0, v + n, np.where(v >= n, v - n, v))
+        assert np.all((r >= 0) & (r < n)), ("wrap", v, n)
+        return r
+
+    def zmod(v):
+        assert np.all(np.asarray(v) >= -3 * nz)
+        return (np.asarray(v) + 3 * nz) % nz
+
+    for b in range(fnyb * nzb):
+        bz = b // fnyb
+        y0 = (b - bz * fnyb) * TYMAX
+        TY = min(TYMAX, ny - y0)      # shorter last tile (general tiles)
+        NI, HC, PR = nx * TY, nx * (TY + 2), TY + 4
+        PC = PR * nx
+        assert PC <= PPT * NT and NI <= IPT * NT and HC <= HPT * NT
+        z0 = bz * SZ
+        z1 = min(z0 + SZ, nz)
+        ring = {}          # slot -> (plane, iteration written; -99 prologue)
+        slot = lambda q: (q - (z0 - 2)) % 5
+
+        def load_pert(q):
+            qz = zmod(q)
+            for j in range(PPT):
+                idx = np.minimum(tid + j * NT, PC - 1)
+                r = idx // nx
+                x = idx - r * nx
+                y = ((y0 + r - 2) % ny + ny) % ny
+                a = qz * nxy + y * nx + x
+                assert np.all((a >= 0) & (a < ncells)), "pert load"
+
+        def store_pert(q, it):
+            for j in range(PPT):
+                idx = np.minimum(tid + j * NT, PC - 1)
+                ri = slot(q) * PC + idx
+                assert np.all((ri >= 0) & (ri < 5 * PC)), "ring store"
+            ring[slot(q)] = (q, it)
+
+        def ring_read(q, r, x, it, phase):
+            assert q - (z0 - 2) >= 0
+            ri = (slot(q) * PR + r) * nx + x
+            assert np.all((r >= 0) & (r < PR)), ("ring row", r)
+            assert np.all((ri >= 0) & (ri < 5 * PC)), "ring read"
+            plane, w_it = ring[slot(q)]
+            assert plane == q, ("ring holds", plane, "wanted", q)
+            # halo reads need the plane written before barrier A of this
+            # iteration; interior reads (after barrier B) may see this one's
+            assert w_it < it or (phase == "interior" and w_it == it), (q, w_it, it, phase)
+
+        def load_plane(p):
+            pz = zmod(p)
+            for h in range(HPT):
+                idx = np.minimum(tid + h * NT, HC - 1)
+                hr = idx // nx
+                x = idx - hr * nx
+                y = wrap(y0 + hr - 1, ny)
+                for i in range(Q):
+                    a = i * S + pz * nxy + y * nx + x
+                    assert np.all((a >= 0) & (a < Q * S)), "pop load"
+
+        for q in range(z0 - 2, z0 + 1):
+            load_pert(q)
+            store_pert(q, -99)
+        load_pert(z0 + 1)
+        pending_pert = z0 + 1
+        load_plane(z0 - 1)
+        for p in range(z0 - 1, z1 + 1):
+            pz = int(wrap(np.array(p), nz))
+            slab = np.zeros((Q, NI), np.int32)
+            store_pert(pending_pert, p)
+            assert pending_pert == p + 2
+            # halo phase
+            for h in range(HPT):
+                idx = np.minimum(tid + h * NT, HC - 1)
+                hr = idx // nx
+                x = idx - hr * nx
+                xm, xp = np.where(x == 0, nx, x) - 1, np.where(x + 1 == nx, 0, x + 1)
+                r = hr + 1
+                for (qq, rr, xx) in ((p, r, x), (p, r, xp), (p, r, xm), (p, r + 1, x),
+                                     (p, r - 1, x), (p + 1, r, x), (p - 1, r, x)):
+                    ring_read(qq, rr, xx, p, "halo")
+                real = tid + h * NT < HC  # lanes past the last halo cell repeat it
+                for i, (cx, cy, cz) in enumerate(lat):
+                    rd = hr - 1 + cy
+                    ok = (rd >= 0) & (rd < TY)
+                    xd = wrap(x + cx, nx)
+                    sidx = rd * nx + xd
+                    assert np.all(~ok | ((sidx >= 0) & (sidx < NI))), "slab push"
+                    np.add.at(slab[i], sidx[ok & real], 1)
+            # every interior cell receives each direction from exactly one halo cell
+            assert np.all(slab == 1), ("slab coverage", slab.min(), slab.max())
+            load_pert(p + 3)
+            pending_pert = p + 3
+            load_plane(p + 1)
+            z = max(p - 1, z0)
+            assert 0 <= z < nz
+            for k in range(IPT):
+                own = (tid + k * NT < NI) & (p > z0)
+                cell = np.minimum(tid + k * NT, NI - 1)
+                r = cell // nx
+                x = cell - r * nx
+                y = y0 + r
+                assert np.all(y < ny)
+                xm, xp = np.where(x == 0, nx, x) - 1, np.where(x + 1 == nx, 0, x + 1)
+                rr = r + 2
+                for (qq, r2, xx) in ((z, rr, x), (z, rr, xp), (z, rr, xm), (z, rr + 1, x),
+                                     (z, rr - 1, x), (z + 1, rr, x), (z - 1, rr, x)):
+                    ring_read(qq, r2, xx, p, "interior")
+                for i, (cx, cy, cz) in enumerate(lat):
+                    yd, zd, xd = wrap(y + cy, ny), int(wrap(np.array(z + cz), nz)), wrap(x + cx, nx)
+                    a = zd * nxy + yd * nx + xd
+                    assert np.all((a >= 0) & (a < ncells))
+                    np.add.at(written[i], a[own], 1)
+        if not full and b > 3:
+            break
+    if full:
+        assert np.all(written == 1), ("coverage", written.min(), written.max())
+    return True
+
+
+
+# (nx, ny, nz, rows per tile, planes per segment)
+CASES = [(64, 8, 6, 1, 4), (64, 8, 6, 2, 32), (64, 8, 6, 4, 1), (64, 8, 6, 8, 3), (128, 4, 5, 2, 2),
+         (64, 2, 1, 2, 8), (64, 1, 2, 1, 1), (192, 6, 7, 3, 5), (256, 4, 9, 4, 4), (128, 12, 3, 6, 2),
+         (64, 3, 2, 3, 1), (64, 1, 1, 1, 1), (128, 2, 3, 1, 7), (256, 8, 3, 2, 64), (256, 8, 5, 4, 64),
+         # general tiles
+         (48, 10, 7, 4, 3), (33, 17, 5, 5, 2), (96, 7, 6, 3, 4), (7, 5, 3, 2, 1), (1, 1, 1, 1, 1),
+         (64, 9, 4, 4, 8), (130, 3, 2, 2, 2), (40, 6, 5, 4, 3), (17, 3, 2, 2, 1), (17, 13, 11, 13, 11),
+         (5, 64, 7, 64, 7), (191, 9, 5, 2, 32), (33, 40, 6, 15, 32)]
+
+
+@pytest.mark.parametrize("lat", ["D3Q19", "D3Q27"])
+@pytest.mark.parametrize("case", CASES)
+def test_two_step_tile_indexing(case, lat):
+    assert check(*case, D3Q19 if lat == "D3Q19" else D3Q27)
+
+
+@pytest.mark.parametrize("case", [(256, 256, 256, 4, 64), (256, 256, 256, 2, 64),
+                                  (128, 128, 128, 4, 8), (512, 64, 16, 2, 8)])
+def test_two_step_tile_indexing_full_size_first_blocks(case):
+    """The first blocks of full-size launches (the 256^3 benchmark shapes)."""
+    assert check(*case, D3Q19, full=False)
