@@ -68,7 +68,7 @@ def measured_traffic(variant, kernel):
 # launch shapes the autotuner picks for this workload on MI355X (used with
 # --fixed-launch, e.g. under a counter profiler that perturbs timing)
 # (tile_x, tile_y, flat, two-step rows, two-step planes)
-FIXED_LAUNCH = {"fp32_shifted": (1024, 1, True, 4, 64), "fp64": (512, 1, True, 2, 64),
+FIXED_LAUNCH = {"fp32_shifted": (1024, 1, True, 4, 64), "fp64": (512, 1, True, 2, 128),
                 "fp16_shifted": (256, 4, False, 4, 64)}
 SINGLE_LAUNCH = {"fp32_shifted": (1024, 1, True, 0, 0), "fp64": (512, 1, True, 0, 0),
                  "fp16_shifted": (256, 4, False, 0, 0)}
