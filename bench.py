@@ -138,51 +138,72 @@ def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
             "steps": steps}
 
 
+Q_OF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+ELEM = {"fp64": (8, 8), "fp32_shifted": (4, 4), "fp16_shifted": (2, 4)}
+
+
+def solo_run(w, variant, steps, warmup=30):
+    """One solve of workload w in storage `variant`, in the launch the
+    autotuner picks (its trial steps are real steps and count as warm-up):
+    MLUPS and the roofline of the launched kernel."""
+    import numpy as np
+    import torch
+
+    from paper_2208_09267_amd import vanse
+
+    dev = torch.device("cuda", 0)
+    q = Q_OF[w.lattice]
+    e, pe = ELEM[variant]
+    bpl = q * e * 2 + pe
+    s = vanse.Solver(w.lattice, w.dims, w.tau, vanse.DTYPES[variant])
+    s.set_porosity(w.eps_mean, torch.from_numpy(w.eps_pert()).to(dev), w.period, w.quad_axes)
+    s.set_force(w.force)
+    s.init(None, torch.from_numpy(np.ascontiguousarray(w.u0())).to(dev))
+    L = s.autotune(4)
+    extra = max(0, warmup - L.steps_run)
+    if L.fused_rows and (s.time + extra) % 2:
+        extra += 1
+    s.step(extra)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    s.close()
+    per_launch = 2 if L.fused_rows else 1
+    gbs = bpl * w.ncells / (ms * per_launch / 1e3) / 1e9
+    return {"mlups": round(w.ncells / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5),
+            "kernel": kernel_name(variant, L.fused_rows, w.lattice),
+            "bytes_per_lup": bpl / per_launch, "gb_s": round(gbs, 1),
+            "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
+            "effective_frac_single_step_bytes":
+                round(bpl * w.ncells / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+            "launch": {"tile_x": L.tile_x, "tile_y": L.tile_y, "flat": bool(L.flags & 4),
+                       "two_step_rows": L.fused_rows, "two_step_planes": L.fused_planes}}
+
+
 def d3q27_run(steps=200, warmup=30):
     """The paper's own 3-D lattice (D3Q27, Table 2) on the same 256^3
     workload: FP64 and FP32 shifted."""
     import dataclasses
 
-    import numpy as np
-    import torch
-
-    from paper_2208_09267_amd import vanse
     from paper_2208_09267_amd import workloads as W
 
     w = dataclasses.replace(W.d3q19_256(), lattice="D3Q27")
-    dev = torch.device("cuda", 0)
-    pert = torch.from_numpy(w.eps_pert()).to(dev)
-    u0 = torch.from_numpy(np.ascontiguousarray(w.u0())).to(dev)
-    out = {}
-    for name, dt, bpl in (("fp64", vanse.FP64, 27 * 8 * 2 + 8),
-                          ("fp32_shifted", vanse.FP32_SHIFTED, 27 * 4 * 2 + 4)):
-        s = vanse.Solver("D3Q27", w.dims, w.tau, dt)
-        s.set_porosity(w.eps_mean, pert, w.period)
-        s.init(None, u0)
-        L = s.autotune(4)
-        extra = max(0, warmup - L.steps_run)
-        if L.fused_rows and (s.time + extra) % 2:
-            extra += 1
-        s.step(extra)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        s.step(steps)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        s.close()
-        per_launch = 2 if L.fused_rows else 1
-        gbs = bpl * w.ncells / (ms * per_launch / 1e3) / 1e9
-        out[name] = {"mlups": round(w.ncells / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5),
-                     "kernel": kernel_name(name, L.fused_rows, "D3Q27"),
-                     "bytes_per_lup": bpl / per_launch, "gb_s": round(gbs, 1),
-                     "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
-                     "effective_frac_single_step_bytes":
-                         round(bpl * w.ncells / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
-                     "launch": {"tile_x": L.tile_x, "tile_y": L.tile_y, "flat": bool(L.flags & 4),
-                                "two_step_rows": L.fused_rows, "two_step_planes": L.fused_planes}}
-    return out
+    return {v: solo_run(w, v, steps, warmup) for v in ("fp64", "fp32_shifted")}
+
+
+def small_configs_run():
+    """The two smaller single-solve workloads, FP64: D2Q9 64^2 (1000 steps;
+    4096 cells, so launch-bound: context only) and D3Q19 128^3 (1000 steps;
+    its 319 MB state partly stays in the 256 MB last-level cache)."""
+    from paper_2208_09267_amd import workloads as W
+
+    return {"d2q9_64": dict(solo_run(W.d2q9_64(), "fp64", 1000), workload="D2Q9 64^2 tau 0.8"),
+            "d3q19_128": dict(solo_run(W.d3q19_128(), "fp64", 1000),
+                              workload="D3Q19 128^3 tau 0.6")}
 
 
 def batched_run(ws=None, steps=500, trial=5, workload=None):
@@ -552,6 +573,8 @@ def main():
     if not args.no_d3q27:
         out["d3q27_256"] = d3q27_run()
         print("# d3q27: %s" % json.dumps(out["d3q27_256"]), file=sys.stderr, flush=True)
+        out["small_configs"] = small_configs_run()
+        print("# small configs: %s" % json.dumps(out["small_configs"]), file=sys.stderr, flush=True)
     if not args.no_batched:
         out["batched"] = batched_run()
         print("# batched: %s" % json.dumps(out["batched"]), file=sys.stderr, flush=True)
