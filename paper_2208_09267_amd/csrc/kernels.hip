@@ -791,9 +791,8 @@ __global__ void __launch_bounds__(NT, (fused_waves_per_simd<L, MODE, IPT, HPT, N
 // its second array (odd launch of a chunk).  GEN: general tiles, each member
 // with its own rows; otherwise every member has the compile-time tile NXC x
 // TYC of the single-solve launch.
-template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN>
-__global__ void __launch_bounds__(kFusedThreads,
-                                  (fused_waves_per_simd<L, MODE, IPT, HPT, NXC, GEN, kFusedThreads>()))
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT>
+__global__ void __launch_bounds__(NT, (fused_waves_per_simd<L, MODE, IPT, HPT, NXC, GEN, NT>()))
     batch_fused2_kernel(const BatchMember *__restrict__ members, const unsigned *__restrict__ owner,
                         const double *__restrict__ mtab, int j, int count, int swap)
 {
@@ -807,7 +806,7 @@ __global__ void __launch_bounds__(kFusedThreads,
         a.f = a.f2;
         a.f2 = t;
     }
-    fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN, kFusedThreads>(a, b - members[s].block_begin);
+    fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN, NT>(a, b - members[s].block_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1152,7 +1151,11 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
         if constexpr (compiled) {
             if (launched || GEN != gen || I != ipt || H != hpt) return;
             if (NXC && (NXC != nx || TYC != ty)) return;
-            auto *fn = &fused2_kernel<L, M, I, H, NXC, TYC, GEN, NTC>;
+            // (I, H) are the cells per thread of a 512-thread block; the
+            // 1024-thread form of the same tile has half as many
+            constexpr int KI = (I * kFusedThreads + NTC - 1) / NTC;
+            constexpr int KH = (H * kFusedThreads + NTC - 1) / NTC;
+            auto *fn = &fused2_kernel<L, M, KI, KH, NXC, TYC, GEN, NTC>;
             // slabs above 64 KiB need the kernel's LDS limit raised, once per device
             static std::atomic<unsigned long long> raised{0};
             int dev = 0;
@@ -1184,8 +1187,11 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
         using F = std::false_type;
         using G = std::true_type;
         using N512 = std::integral_constant<int, kFusedThreads>;
+        using N1024 = std::integral_constant<int, 2 * kFusedThreads>;
         if constexpr (std::is_same<L, D3Q19>::value) {
-            go(lat, mode, C2{}, C3{}, C256{}, C4{}, F{}, N512{});
+            // the 256 x 4 tile in 1024-thread blocks (one interior and two halo
+            // cells per thread, 4 waves per SIMD; FP64 has no such tile)
+            go(lat, mode, C2{}, C3{}, C256{}, C4{}, F{}, N1024{});
             go(lat, mode, C1{}, C2{}, C256{}, C2{}, F{}, N512{});
             go(lat, mode, C1{}, C2{}, C128{}, C4{}, F{}, N512{});
         } else {
@@ -1246,21 +1252,25 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, u
     if (lattice == 0 || lds > (size_t)kFusedMaxLds) return hipErrorInvalidValue;
     hipError_t rc = hipErrorInvalidValue;
     bool launched = false;
-    // one instantiation: IPT, HPT, compile-time nx / rows (0, 0: general tiles)
-    auto go = [&](auto lat, auto m, auto ic, auto hc, auto nxc, auto tyc) {
+    // one instantiation: IPT, HPT (of a 512-thread block), compile-time nx /
+    // rows (0, 0: general tiles), threads per block
+    auto go = [&](auto lat, auto m, auto ic, auto hc, auto nxc, auto tyc, auto ntc) {
         using L = decltype(lat);
         constexpr int M = decltype(m)::value;
         constexpr int I = decltype(ic)::value;
         constexpr int H = decltype(hc)::value;
         constexpr int NXC = decltype(nxc)::value;
         constexpr int TYC = decltype(tyc)::value;
+        constexpr int NTC = decltype(ntc)::value;
+        constexpr int KI = (I * kFusedThreads + NTC - 1) / NTC;
+        constexpr int KH = (H * kFusedThreads + NTC - 1) / NTC;
         constexpr bool GEN = NXC == 0;
         constexpr int LAT = std::is_same<L, D3Q19>::value ? 1 : 2;
         constexpr bool compiled =
             GEN ? fused_compiled_gen(LAT, M, I, H) : fused_compiled(LAT, M, I, H, NXC);
         if constexpr (compiled) {
             if (launched || NXC != uni_nx || TYC != uni_rows) return;
-            auto *fn = &batch_fused2_kernel<L, M, I, H, NXC, TYC, GEN>;
+            auto *fn = &batch_fused2_kernel<L, M, KI, KH, NXC, TYC, GEN, NTC>;
             static std::atomic<unsigned long long> raised{0};
             int dev = 0;
             if ((rc = hipGetDevice(&dev)) != hipSuccess) return;
@@ -1271,7 +1281,7 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, u
                 if (rc != hipSuccess) return;
                 raised.fetch_or(bit);
             }
-            fn<<<nblocks, kFusedThreads, lds, st>>>(members, owner, mtab, j, count, swap);
+            fn<<<nblocks, NTC, lds, st>>>(members, owner, mtab, j, count, swap);
             rc = hipGetLastError();
             launched = true;
         }
@@ -1289,15 +1299,17 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, u
         if constexpr (L::D == 3) {
             // general tiles: one interior and two halo cells per thread (FP64:
             // one); the compile-time tiles of batch_uniform_rows
-            if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{});
-            else go(lat, m, C1{}, C2{}, C0{}, C0{});
+            using N512 = std::integral_constant<int, kFusedThreads>;
+            using N1024 = std::integral_constant<int, 2 * kFusedThreads>;
+            if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{}, N512{});
+            else go(lat, m, C1{}, C2{}, C0{}, C0{}, N512{});
             if constexpr (std::is_same<L, D3Q19>::value) {
-                go(lat, m, C2{}, C3{}, C256{}, C4{});
-                go(lat, m, C1{}, C2{}, C256{}, C2{});
-                go(lat, m, C1{}, C2{}, C128{}, C4{});
+                go(lat, m, C2{}, C3{}, C256{}, C4{}, N1024{});
+                go(lat, m, C1{}, C2{}, C256{}, C2{}, N512{});
+                go(lat, m, C1{}, C2{}, C128{}, C4{}, N512{});
             } else {
-                go(lat, m, C2{}, C3{}, C256{}, C4{});
-                go(lat, m, C1{}, C2{}, C256{}, C2{});
+                go(lat, m, C2{}, C3{}, C256{}, C4{}, N512{});
+                go(lat, m, C1{}, C2{}, C256{}, C2{}, N512{});
             }
         }
         return hipSuccess;

@@ -24,14 +24,13 @@ import itertools
 import numpy as np
 import pytest
 
-NT = 512
 D3Q19 = [(0,0,0),(1,0,0),(0,1,0),(0,0,1),(1,1,0),(1,-1,0),(1,0,1),(1,0,-1),(0,1,1),(0,1,-1),
          (-1,0,0),(0,-1,0),(0,0,-1),(-1,-1,0),(-1,1,0),(-1,0,-1),(-1,0,1),(0,-1,-1),(0,-1,1)]
 D3Q27 = [(0,0,0)] + [c for c in itertools.product((-1,0,1), repeat=3) if c != (0,0,0) and c > (0,0,0)]
 D3Q27 = D3Q27 + [tuple(-v for v in c) for c in D3Q27[1:]]
 
 
-def check(nx, ny, nz, TY, SZ, lat, full=True):
+def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
     Q = len(lat)
     ncells = nx * ny * nz
     S = (ncells + 127) // 128 * 128
@@ -186,3 +185,11 @@ def test_two_step_tile_indexing(case, lat):
 def test_two_step_tile_indexing_full_size_first_blocks(case):
     """The first blocks of full-size launches (the 256^3 benchmark shapes)."""
     assert check(*case, D3Q19, full=False)
+
+
+@pytest.mark.parametrize("case", [(256, 8, 5, 4, 64), (256, 4, 9, 4, 4), (256, 12, 3, 4, 2)])
+def test_two_step_tile_indexing_1024_threads(case):
+    """The 256 x 4 tile in 1024-thread blocks (one interior, two halo cells
+    per thread, the second halo cell of half the threads past the tile)."""
+    assert check(*case, D3Q19, NT=1024)
+    assert check(256, 256, 256, 4, 64, D3Q19, full=False, NT=1024)
