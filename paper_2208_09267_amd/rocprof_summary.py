@@ -9,6 +9,7 @@ run.
 
 Usage (repository root):
   python -m paper_2208_09267_amd.rocprof_summary stats DIR
+  python -m paper_2208_09267_amd.rocprof_summary trace DIR
   python -m paper_2208_09267_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR [FETCH_DIR WRITE_DIR ...] OUT_JSON
 """
 from __future__ import annotations
@@ -151,7 +152,73 @@ def stats(directory):
     return rows
 
 
+# cells of the bench.py workloads a kernel launch of the kernel trace belongs to
+_BATCH64_CELLS = 22179840        # the 64-solve batch
+_BATCH256_CELLS = 4 * 256 ** 3   # four 256^3 solves
+
+
+def _workload(short, grid):
+    """(workload name, cells) of a launch in a bench.py run, from the kernel
+    name and its grid size; (None, None) for other kernels."""
+    lat = "D2Q9" if "D2Q9" in short else ("D3Q27" if "D3Q27" in short else "D3Q19")
+    if short.startswith("batch_fused2"):
+        if ", 256, 4" in short:
+            return "4 x 256^3 batch", _BATCH256_CELLS
+        return "64-solve batch", _BATCH64_CELLS
+    if short.startswith("batch_step"):
+        if grid >= _BATCH256_CELLS - 1024:
+            return "4 x 256^3 batch", _BATCH256_CELLS
+        return "64-solve batch", _BATCH64_CELLS
+    if lat == "D2Q9" and short.startswith("step_kernel"):
+        return "D2Q9 64^2", 64 * 64
+    if short.startswith("fused2"):
+        return ("D3Q19 128^3", 128 ** 3) if ", 128, 4" in short else (lat + " 256^3", 256 ** 3)
+    if short.startswith("step_kernel"):
+        return ("D3Q19 128^3", 128 ** 3) if grid < 4000000 else (lat + " 256^3", 256 ** 3)
+    return None, None
+
+
+def trace(directory, min_calls=50):
+    """Rows of (kernel, workload, calls, average us, min us, max us,
+    algorithmic GB/s, MLUPS) from a --kernel-trace run of bench.py, grouped by
+    kernel and grid size (groups with fewer calls are autotuner trials)."""
+    groups = {}
+    with open(_one(os.path.join(directory, "*kernel_trace.csv"))) as fh:
+        for row in csv.DictReader(fh):
+            name = row["Kernel_Name"]
+            if "vanse::" not in name:
+                continue
+            short = re.sub(r"\(.*\)$", "", name).replace("void ", "").replace("vanse::", "")
+            us = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3
+            groups.setdefault((short, int(row["Grid_Size_X"])), []).append(us)
+    rows = []
+    for (short, grid), d in groups.items():
+        if len(d) < min_calls:
+            continue
+        avg = sum(d) / len(d)
+        wl, cells = _workload(short, grid)
+        m = re.match(r"(\w+)<(D\dQ\d+), (\d)", short)
+        gbs = mlups = None
+        if wl is not None and m:
+            q = LATTICE_Q[m.group(2)]
+            mode = int(m.group(3))
+            lups = (2 if "fused2" in short else 1) * cells
+            gbs = (2 * q * ELEM[mode] + PERT[mode]) * cells / (avg * 1e-6) / 1e9
+            mlups = lups / (avg * 1e-6) / 1e6
+        rows.append((short, wl, len(d), avg, min(d), max(d), gbs, mlups))
+    return sorted(rows, key=lambda r: (r[1] or "~", r[0]))
+
+
 def main(argv):
+    if len(argv) >= 2 and argv[0] == "trace":
+        for k, wl, n, avg, mn, mx, gbs, mlups in trace(argv[1]):
+            launch_bound = wl == "D2Q9 64^2"
+            print("| `%s` | %s | %d | %.1f | %.1f | %.1f | %s | %s |"
+                  % (k, wl or "—", n, avg, mn, mx,
+                     "—" if gbs is None or launch_bound else "%.0f" % gbs,
+                     "—" if mlups is None else ("%.0f" % mlups) +
+                     (" (launch-bound)" if launch_bound else "")))
+        return 0
     if len(argv) >= 2 and argv[0] == "stats":
         for r in stats(argv[1]):
             print("| `%s` | %d | %.1f | %.1f | %.1f |" % r)
