@@ -100,9 +100,12 @@ def test_example1_stationary_2d_second_order_fine():
 
 @pytest.mark.slow
 def test_example4_transient_2d_second_order():
-    # N = 32 alone settles into a state far from the manufactured solution
-    # (N = 30, 31, 33, 34, 36 do not); the series avoids it.
-    _check_second_order(4, [16, 24, 36], 0.5075, 40.0)
+    # Second order in every norm holds in the asymptotic range: from N = 24 to
+    # 36 the pressure maximum norm still converges at 1.6 (the L1/L2 norms and
+    # the velocity at 1.8-2.0); from 36 to 48 every norm gives 2.0-2.1 (and
+    # from 48 to 72, 2.0).  N = 32 alone settles into a state far from the
+    # manufactured solution (N = 30, 31, 33, 34, 36 do not); the series avoids it.
+    _check_second_order(4, [36, 48], 0.5075, 40.0)
 
 
 @pytest.mark.slow
