@@ -115,7 +115,10 @@ def test_example2_stationary_3d_second_order():
 
 @pytest.mark.slow
 def test_example5_transient_3d_second_order():
-    _check_second_order(5, [16, 24], 0.5075, 40.0)
+    # From N = 16 to 24 the pressure maximum norm converges at 1.3 (every other
+    # norm at 1.8-2.1); from 24 to 32 every norm gives 1.8-2.1.  About an hour
+    # on 8 cores.
+    _check_second_order(5, [24, 32], 0.5075, 40.0)
 
 
 def test_pressure_needs_the_cell_integral():
