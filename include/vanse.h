@@ -269,7 +269,10 @@ int vanse_set_tile(vanse_t h, int tile_x, int tile_y);
  *   D3Q27, FP32/FP16 storage: I = 1 and H <= 2
  *   D3Q27, FP64: none;
  * and the block's LDS (Q * nx * rows stored populations plus 5 * (rows + 4)
- * * nx perturbation values) within 160 KiB.
+ * * nx perturbation values) within 160 KiB.  Blocks have 512 threads, except
+ * D3Q19's 256-wide 4-row tile in FP32/FP16 storage, which runs in blocks of
+ * 1024 threads (one interior and two halo cells per thread; the FP16 form
+ * spills a few registers and still measured faster).
  * rows = 0 switches the launch off and frees the second array.
  * Synchronises the solver's stream when it allocates or frees.
  * Errors: EINVAL, ENOMEM. */
@@ -279,8 +282,8 @@ int vanse_set_fused(vanse_t h, int rows, int planes);
  * row segments with 1, 2 or 4 rows per block where they divide the
  * lattice; flat launches of 256, 512 and 1024 threads; on 3-D lattices the
  * two-step launch of vanse_set_fused with 1, 2, 4 or 8 rows and 8, 32 or
- * 64 planes, and 128 when nz > 64, where its shape exists) runs `steps_per_trial` REAL steps timed
- * with HIP events, and the fastest is kept and cached for solves of the same
+ * 64 planes, and 128 when nz > 64, where its shape exists) runs
+ * `steps_per_trial` REAL steps timed with HIP events, and the fastest is kept and cached for solves of the same
  * lattice, dtype and size class.  *fused_rows / *fused_planes report the
  * chosen two-step tile (0 / 0: single steps; the tile of the single-step
  * kernel is still reported and used for leftover steps).  The two-step
