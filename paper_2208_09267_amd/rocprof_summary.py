@@ -10,6 +10,7 @@ run.
 Usage (repository root):
   python -m paper_2208_09267_amd.rocprof_summary stats DIR
   python -m paper_2208_09267_amd.rocprof_summary trace DIR
+  python -m paper_2208_09267_amd.rocprof_summary sq DIR [DIR ...]
   python -m paper_2208_09267_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR [FETCH_DIR WRITE_DIR ...] OUT_JSON
 """
 from __future__ import annotations
@@ -209,7 +210,46 @@ def trace(directory, min_calls=50):
     return sorted(rows, key=lambda r: (r[1] or "~", r[0]))
 
 
+def sq(directories):
+    """Per-kernel mean of every SQ counter in the given --pmc runs (one
+    counter group per run), for the step kernels; with the derived shares of
+    a wave's lifetime spent issuing VALU instructions, issuing anything, and
+    waiting on a memory or LDS result (the SQ_*_CYCLES-type counters are
+    in the same units, so their ratios are unit-free)."""
+    per = {}
+    for d in directories:
+        with open(_one(os.path.join(d, "*counter_collection.csv"))) as fh:
+            for row in csv.DictReader(fh):
+                p = parse_name(row["Kernel_Name"])
+                if p is None:
+                    continue
+                per.setdefault(p[0], {}).setdefault(row["Counter_Name"], []).append(
+                    float(row["Counter_Value"]))
+    out = {}
+    for label, cs in per.items():
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        wc = m.get("SQ_WAVE_CYCLES")
+        if wc:
+            for c, share in (("SQ_ACTIVE_INST_VALU", "valu_share"),
+                             ("SQ_ACTIVE_INST_ANY", "issue_share"),
+                             ("SQ_WAIT_INST_ANY", "wait_share"),
+                             ("SQ_ACTIVE_INST_SCA", "salu_share"),
+                             ("SQ_ACTIVE_INST_LDS", "lds_share")):
+                if c in m:
+                    m[share] = m[c] / wc
+        if "SQ_WAVES" in m and wc:
+            m["wave_cycles_per_wave"] = wc / m["SQ_WAVES"]
+        out[label] = m
+    return out
+
+
 def main(argv):
+    if len(argv) >= 2 and argv[0] == "sq":
+        for label, m in sorted(sq(argv[1:]).items()):
+            print(label)
+            for k in sorted(m):
+                print("  %-28s %.4g" % (k, m[k]))
+        return 0
     if len(argv) >= 2 and argv[0] == "trace":
         for k, wl, n, avg, mn, mx, gbs, mlups in trace(argv[1]):
             launch_bound = wl == "D2Q9 64^2"
