@@ -279,12 +279,22 @@ __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R o
         }
     });
     const R M0 = St::shifted ? R(1) + s0 : s0;
-    const R rho = M0 / I;               // eq. density
+    // eq. density and the 1/M0 of eq. velocity.  In FP16 storage, whose
+    // rounding dominates the error, the hardware reciprocal (about 1 ulp of
+    // FP32) replaces the two correctly rounded divisions: the FP16 step is
+    // bound by its arithmetic, of which they are about a tenth.
+    R rho, inv;
+    if constexpr (MODE == MODE_F16S) {
+        rho = M0 * __builtin_amdgcn_rcpf(I);
+        inv = __builtin_amdgcn_rcpf(M0);
+    } else {
+        rho = M0 / I;
+        inv = R(1) / M0;
+    }
     const R p = rho * R(1.0 / 3.0);     // p = rho c_s^2
     const R Fx = p * gx + Fex;          // F_PC + F_ext (eq. pressForce)
     const R Fy = p * gy + Fey;
     const R Fz = (L::D == 3) ? p * gz + Fez : R(0);
-    const R inv = R(1) / M0;
     const R ux = (jx + R(0.5) * Fx) * inv;  // eq. velocity
     const R uy = (jy + R(0.5) * Fy) * inv;
     const R uz = (L::D == 3) ? (jz + R(0.5) * Fz) * inv : R(0);
