@@ -271,8 +271,7 @@ int vanse_set_tile(vanse_t h, int tile_x, int tile_y);
  * and the block's LDS (Q * nx * rows stored populations plus 5 * (rows + 4)
  * * nx perturbation values) within 160 KiB.  Blocks have 512 threads, except
  * D3Q19's 256-wide 4-row tile in FP32/FP16 storage, which runs in blocks of
- * 1024 threads (one interior and two halo cells per thread; the FP16 form
- * spills a few registers and still measured faster).
+ * 1024 threads (one interior and two halo cells per thread).
  * rows = 0 switches the launch off and frees the second array.
  * Synchronises the solver's stream when it allocates or frees.
  * Errors: EINVAL, ENOMEM. */

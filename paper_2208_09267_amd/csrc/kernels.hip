@@ -520,7 +520,9 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
     // trash slot
     constexpr bool EXACT = !GEN && NXC > 0 && TYC > 0 && NXC * TYC == IPT * NT;
     constexpr int RING = 5;                 // pert planes p-2 .. p+2
-    constexpr int PPT = (5 * HPT + 2) / 3;  // pert values per thread and plane
+    // pert values per thread and plane: exact for the compile-time tiles,
+    // else a bound from the halo cells per thread ((rows + 4) / (rows + 2) <= 5/3)
+    constexpr int PPT = (NXC > 0 && TYC > 0) ? ((TYC + 4) * NXC + NT - 1) / NT : (5 * HPT + 2) / 3;
     extern __shared__ __align__(16) unsigned char fused_lds[];
 
     const int nx = NXC ? NXC : a.geo.nx, ny = a.geo.ny, nz = a.geo.nz, nxy = a.geo.nxy;

@@ -37,7 +37,13 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
     nxy = nx * ny
     TYMAX = TY
     IPT, HPT = -(-nx * TY // NT), -(-nx * (TY + 2) // NT)
-    PPT = (5 * HPT + 2) // 3
+    # pert values per thread: exact for the compile-time tiles (256 x 4,
+    # 256 x 2, 128 x 4 for D3Q19; 256 x 4, 256 x 2 for D3Q27), else a bound
+    tiles = {(256, 4), (256, 2), (128, 4)} if Q == 19 else {(256, 4), (256, 2)}
+    if (nx, TY) in tiles and ny % TY == 0:
+        PPT = -(-(TY + 4) * nx // NT)
+    else:
+        PPT = (5 * HPT + 2) // 3
     fnyb = -(-ny // TY)
     nzb = -(-nz // SZ)
     tid = np.arange(NT)
