@@ -393,6 +393,8 @@ def serve_run(rate, duration, budget, cell_cap, seed=4):
                 "chunks": srv.stats["chunks"],
                 "batch_steps_by_tuning": {"two_step": srv.stats["steps_two_step_tuning"],
                                           "single_step": srv.stats["steps_single_step_tuning"]},
+                "lattice_updates_by_tuning": {"two_step": srv.stats["lups_two_step_tuning"],
+                                              "single_step": srv.stats["lups_single_step_tuning"]},
                 "loop_seconds": {k: round(v, 2) for k, v in srv.time.items()}})
     return out
 

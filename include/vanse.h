@@ -223,7 +223,9 @@ int vanse_batch_step(vanse_batch_t b, int64_t n);
  * candidate (steps_per_trial rounded up to even) each run twice in a row,
  * the faster run of each counting; the fastest per step is kept and cached for batches of the same
  * lattice, dtype and size class (not cached when the members' time levels
- * differ in parity, which leaves the two-step candidate untried).  Members advance
+ * differ in parity, which leaves the two-step candidate untried).  A cached
+ * choice answers calls with at most the steps_per_trial that made it; a call
+ * with longer trials runs them again and replaces it.  Members advance
  * the steps of every trial (0 if the choice came from the cache; *steps_run
  * tells).  Second population arrays allocated for the two-step trial stay
  * with the members.  Synchronises. */

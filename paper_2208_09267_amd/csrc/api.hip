@@ -652,7 +652,11 @@ namespace {
 
 thread_local std::string g_batch_error;
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune_cache;  // (lat, mode, log2 cells)
+// (lat, mode, log2 cells) -> block, flags and the steps per trial that chose them
+struct TuneChoice {
+    int block, flags, trial;
+};
+std::map<std::tuple<int, int, int>, TuneChoice> g_tune_cache;
 
 int bfail(vanse_batch *b, int code, const std::string &msg)
 {
@@ -1118,9 +1122,10 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            best_block = it->second.first;
-            best_flags = it->second.second;
+        // a choice made on shorter trials than these is tried again
+        if (it != g_tune_cache.end() && it->second.trial >= steps_per_trial) {
+            best_block = it->second.block;
+            best_flags = it->second.flags;
             cached = true;
         }
     }
@@ -1198,7 +1203,7 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
         if (rc != VANSE_OK) return rc;
         if (cache) {
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tune_cache[key] = {best_block, best_flags};
+            g_tune_cache[key] = {best_block, best_flags, steps_per_trial};
         }
     }
     int rc = vanse_batch_set_tuning(b, best_block, best_flags, b->chunk);

@@ -87,6 +87,23 @@ def steps_until_host(min_remaining: int, chunk: int, queue_waiting: bool,
     return min_remaining
 
 
+def tune_trial_steps(min_remaining: int, longest: int = 16) -> int:
+    """Steps per autotuner trial that keep all of its real steps (at most
+    10 t + 9 for t steps per trial) within the fewest steps any member has
+    left; 0 when not even a one-step trial fits."""
+    return max(0, min(longest, (min_remaining - 9) // 10))
+
+
+def retune(prev_trial: int, trial: int, longest: int = 16) -> bool:
+    """Whether to autotune a size class now: it has no choice yet
+    (prev_trial 0) and a trial fits, or its choice came from trials shorter
+    than the longest and a longest trial fits now (short trials do not
+    resolve launches a few percent apart)."""
+    if trial < 1:
+        return False
+    return prev_trial == 0 or (prev_trial < longest and trial >= longest)
+
+
 @dataclasses.dataclass
 class Result:
     rid: int
@@ -236,15 +253,19 @@ class Server:
                     # cells); a class without a choice yet is tuned when the
                     # trials fit, otherwise it takes the default launch
                     cls = sum(a.work.ncells for a in active).bit_length() - 1
-                    block, flags = self._tuned.get(cls, self.tuning)
+                    prev = self._tuned.get(cls)
+                    block, flags = prev[:2] if prev else self.tuning
                     # trial steps are real steps: keep them within every member's count
                     # (6 single-step trials of t, one aligning step, then twice a
-                    # two-step trial of 4 and a single-step one of t rounded up to
-                    # even: at most 8 t + 11 steps for t <= 4)
-                    trial = min(4, (min(a.remaining for a in active) - 11) // 8)
-                    if cls not in self._tuned and trial >= 1:
+                    # two-step trial of t rounded up to a multiple of 4 and a
+                    # single-step one of t rounded up to even: at most 10 t + 9
+                    # steps).  Longer trials resolve launches that differ by a few
+                    # percent on small batches, where a trial of a few steps lasts
+                    # well under a millisecond.
+                    trial = tune_trial_steps(min(a.remaining for a in active))
+                    if retune(prev[2] if prev else 0, trial):
                         block, flags, ran = batch.autotune(trial)
-                        self._tuned[cls] = (block, flags)
+                        self._tuned[cls] = (block, flags, trial)
                         for a in active:
                             a.remaining -= ran
                 if not self.two_step:
@@ -261,9 +282,11 @@ class Server:
                 for a in active:
                     a.remaining -= step
                 self.stats["chunks"] += 1
-                # batch steps taken under a two-step or a single-step tuning
-                two = self.two_step and flags & vanse.TUNE_TWO_STEP
-                self.stats["steps_two_step_tuning" if two else "steps_single_step_tuning"] += step
+                # batch steps and lattice updates taken under a two-step or a
+                # single-step tuning
+                kind = "two_step" if self.two_step and flags & vanse.TUNE_TWO_STEP else "single_step"
+                self.stats["steps_" + kind + "_tuning"] += step
+                self.stats["lups_" + kind + "_tuning"] += step * sum(a.work.ncells for a in active)
             torch.cuda.current_stream().synchronize()
             self.time["step"] += clock() - ts
             done = [a for a in active if a.remaining <= 0]

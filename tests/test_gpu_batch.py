@@ -71,6 +71,9 @@ def test_autotune_keeps_results_bitwise():
     # second batch of the same size class: the choice comes from the cache
     b2 = vanse.Batch(members)
     assert b2.autotune(2) == (block, flags, 0)
+    assert b2.autotune(1) == (block, flags, 0)  # shorter trials: the cached choice
+    assert b2.autotune(3)[2] >= 6 * 3           # longer trials run again
+    assert b2.autotune(3)[2] == 0               # and replace it
     b2.close()
     for s in solo + members:
         s.close()

@@ -54,3 +54,33 @@ def test_state_bytes_formula(dtype, elem, pert):
     assert serve.state_bytes("D3Q19", (33, 17, 5), dtype, two_step=True) == want + 19 * stride * elem
     assert serve.state_bytes("D2Q9", (33, 17, 1), dtype, two_step=True) == \
         serve.state_bytes("D2Q9", (33, 17, 1), dtype)
+
+
+def _autotune_steps(t, odd_start):
+    """Real steps vanse_batch_autotune takes with t steps per trial: six
+    single-step trials, one aligning step when the members sit at an odd
+    level, then twice a two-step trial (t rounded up to a multiple of 4) and
+    twice the best single-step candidate (t rounded up to even)."""
+    return 6 * t + (1 if (odd_start + 6 * t) % 2 else 0) + 2 * ((t + 3) // 4 * 4) + 2 * ((t + 1) // 2 * 2)
+
+
+def test_tune_trial_steps_stay_within_every_member():
+    assert serve.tune_trial_steps(10_000) == 16
+    assert serve.tune_trial_steps(18) == 0
+    assert serve.tune_trial_steps(19) == 1
+    assert serve.tune_trial_steps(500, longest=4) == 4
+    for m in range(0, 400):
+        t = serve.tune_trial_steps(m)
+        assert 0 <= t <= 16
+        if t:
+            assert max(_autotune_steps(t, o) for o in (0, 1)) <= m
+    # the 2-step trial of the GPU autotune test: 12 + 2 * (4 + 2)
+    assert _autotune_steps(2, 0) == 24
+
+
+def test_retune_rule():
+    assert serve.retune(0, 16) and serve.retune(0, 3)   # no choice yet, a trial fits
+    assert not serve.retune(0, 0)                       # nothing fits
+    assert not serve.retune(16, 16)                     # a full-length choice stays
+    assert not serve.retune(3, 8)                       # still short: keep the choice
+    assert serve.retune(3, 16)                          # short choice, full trial fits now
