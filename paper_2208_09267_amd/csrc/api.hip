@@ -10,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <queue>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -711,13 +712,84 @@ hipError_t batch_tables(vanse_batch *b)
     return e;
 }
 
+// nz split into equal z-segments of at most `target` planes: planes per segment.
+int balanced_planes(int nz, int target)
+{
+    const int segs = (nz + target - 1) / target;
+    return (nz + segs - 1) / segs;
+}
+
+// Estimated duration (in cell-planes) of a batched two-step launch of general
+// tiles whose segments aim at `target` planes.  Blocks reach the XCDs in
+// contiguous ranges of the block index (the kernel's XCD-contiguous order),
+// and within an XCD each block starts on the CU that frees first (one block
+// of the general tile per CU); a block costs its tile's cells per plane times
+// its planes plus 3, the planes a segment reads and collides beyond its own.
+double gen_launch_estimate(const std::vector<const vanse::Solver *> &ms,
+                           const std::vector<int> &rows, int target, int cus)
+{
+    std::vector<double> cost;
+    for (size_t k = 0; k < ms.size(); ++k) {
+        const vanse::Geometry &g = ms[k]->geo;
+        const int r = rows[k], P = balanced_planes(g.nz, target), fnyb = (g.ny + r - 1) / r;
+        for (int z0 = 0; z0 < g.nz; z0 += P)
+            for (int yb = 0; yb < fnyb; ++yb)
+                cost.push_back(double(std::min(P, g.nz - z0) + 3) * std::min(r, g.ny - yb * r) * g.nx);
+    }
+    const size_t n = cost.size(), q = n / 8, rem = n % 8;
+    const int per_xcd = std::max(1, cus / 8);
+    double span = 0.0;
+    size_t begin = 0;
+    for (size_t x = 0; x < 8; ++x) {
+        const size_t cnt = q + (x < rem ? 1 : 0);
+        std::priority_queue<double, std::vector<double>, std::greater<double>> free_at;
+        for (int c = 0; c < per_xcd; ++c) free_at.push(0.0);
+        double last = 0.0;
+        for (size_t i = begin; i < begin + cnt; ++i) {
+            const double t = free_at.top() + cost[i];
+            free_at.pop();
+            free_at.push(t);
+            last = std::max(last, t);
+        }
+        span = std::max(span, last);
+        begin += cnt;
+    }
+    return span;
+}
+
+// Segment target of the general tiles: 32 planes, or 24 or 16 when the
+// estimate above predicts the launch at least 8% faster with them (a batch
+// with too few tiles to fill the chip gains more from extra blocks than it
+// loses to the extra planes of shorter segments; measured on mixed batches of
+// 2-26 M cells, the rule picks the fastest target or one within 3% of it).
+int gen_segment_target(const std::vector<const vanse::Solver *> &ms, const std::vector<int> &rows)
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
+        cus = 256;
+    const double base = gen_launch_estimate(ms, rows, 32, cus);
+    int best = 32;
+    double best_t = base;
+    for (int target : {24, 16}) {
+        const double t = gen_launch_estimate(ms, rows, target, cus);
+        if (t < best_t) {
+            best_t = t;
+            best = target;
+        }
+    }
+    return best_t <= base / 1.08 ? best : 32;
+}
+
 // Two-step tables: a tile per member, its second population array
 // (allocated when missing; the member's solver keeps it), and the owner table
 // of that grid.  When every member has the same nx and a compile-time tile of
 // that width divides its ny (batch_uniform_rows), all use that tile with
 // segments of 64 planes, as a single solve would; otherwise each member gets
-// a general tile (batch_fused_rows x-rows, segments of 32 planes).  Leaves
-// fused_ok false (single steps only) when a member has no tile.
+// a general tile (batch_fused_rows x-rows) and its nz is split into equal
+// segments of at most 32 planes (24 or 16 for batches too small to fill the
+// chip, gen_segment_target).  Leaves fused_ok false (single steps only) when
+// a member has no tile.
 int batch_layout2(vanse_batch *b)
 {
     b->fused_ok = false;
@@ -741,7 +813,22 @@ int batch_layout2(vanse_batch *b)
     auto tile_rows = [&](const Solver &s) {
         return uni_rows ? uni_rows : vanse::batch_fused_rows(s);
     };
-    auto tile_planes = [&](const Solver &s) { return std::min(uni_rows ? 64 : 32, s.geo.nz); };
+    int gen_target = 32;
+    if (!uni_rows) {
+        std::vector<const Solver *> ms;
+        std::vector<int> rows;
+        for (int k = 0; k < b->count; ++k) {
+            const Solver &s = b->members[k]->s;
+            const int r = vanse::batch_fused_rows(s);
+            if (r == 0) return VANSE_OK;  // no tile: single steps only
+            ms.push_back(&s);
+            rows.push_back(r);
+        }
+        gen_target = gen_segment_target(ms, rows);
+    }
+    auto tile_planes = [&](const Solver &s) {
+        return uni_rows ? std::min(64, s.geo.nz) : balanced_planes(s.geo.nz, gen_target);
+    };
     std::vector<vanse::BatchMember> mem(b->count);
     std::vector<unsigned> owner;
     unsigned begin = 0;
