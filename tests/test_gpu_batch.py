@@ -11,6 +11,8 @@ from paper_2208_09267_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
+# small enough that the general tiles of the batched two-step launch take
+# 16-plane z-segments (the batch cannot fill the GPU with 32)
 CASES = [((17, 13, 11), 0.57, 1), ((32, 32, 32), 0.9, 2), ((48, 40, 36), 0.66, 3),
          ((5, 64, 7), 0.75, 4), ((64, 8, 9), 1.2, 5)]
 
