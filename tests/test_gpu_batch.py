@@ -237,3 +237,32 @@ def test_two_step_batch_compile_time_tiles_bitwise(group, lat, dtype):
     b.close()
     for s in members:
         s.close()
+
+
+@pytest.mark.parametrize("dtype", [vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+def test_two_step_batch_24_plane_segments_bitwise(dtype):
+    """Four requests of the served stream's sizes (edges 80, 63, 153, 69:
+    4.7 M cells) have too few general tiles to fill the GPU with 32-plane
+    z-segments; the batched launch splits their nz into equal segments of at
+    most 24 planes (153: 7 of 22, 80: 4 of 20), and every member still
+    equals the solve stepped alone."""
+    print("case 24-plane segments", dtype, flush=True)
+    cases = [((80, 80, 80), 0.6, 21), ((63, 63, 63), 0.85, 22), ((153, 153, 153), 0.7, 23),
+             ((69, 69, 69), 0.95, 24)]
+    steps = 21
+    solo = [_make_lat("D3Q19", d, t, s, dtype) for d, t, s in cases]
+    for s in solo:
+        s.step(steps)
+    want = [s.populations().cpu().numpy() for s in solo]
+    for s in solo:
+        s.close()
+    members = [_make_lat("D3Q19", d, t, s, dtype) for d, t, s in cases]
+    b = vanse.Batch(members)
+    b.set_tuning(256, vanse.TUNE_TWO_STEP, 16)
+    b.step(steps)
+    for k, s in enumerate(members):
+        assert s.time == steps
+        assert np.array_equal(s.populations().cpu().numpy(), want[k]), k
+    b.close()
+    for s in members:
+        s.close()
