@@ -234,6 +234,16 @@ int vanse_batch_step(vanse_batch_t b, int64_t n);
 int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *flags,
                          int64_t *steps_run);
 
+/* The two-step layout in effect (VANSE_TUNE_TWO_STEP set by
+ * vanse_batch_set_tuning or chosen by vanse_batch_autotune): for member k, in
+ * the order the members were given, rows[k] full x-rows per tile and
+ * planes[k] z-planes per segment (the last segment may be shorter).  rows
+ * and planes are caller-owned host arrays of `count` ints; count must equal
+ * the number of members (VANSE_EINVAL otherwise).  VANSE_ESTATE when no
+ * two-step layout is in effect (the flag is not set, the lattice is 2-D, or a
+ * member has no tile).  Host only: no GPU work. */
+int vanse_batch_two_step_layout(vanse_batch_t b, int count, int *rows, int *planes);
+
 /* Last error message of b (NULL: of the last failed vanse_batch_create). */
 const char *vanse_batch_last_error(vanse_batch_t b);
 

@@ -54,6 +54,7 @@ struct vanse_batch {
     unsigned *d_owner2 = nullptr;
     size_t d_members2_cap = 0, cap_owner2 = 0;
     std::vector<void *> layout_f2;      // members' second arrays in the two-step table
+    std::vector<int> rows2, planes2;    // members' tile rows and z-planes per segment
     hipGraphExec_t gexec2 = nullptr;    // a full chunk of two-step launches
 };
 
@@ -891,6 +892,12 @@ int batch_layout2(vanse_batch *b)
         (e = hipMemcpy(b->d_owner2, owner.data(), sizeof(unsigned) * owner.size(),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return bfail(b, VANSE_EDEVICE, std::string("vanse_batch: upload: ") + hipGetErrorString(e));
+    b->rows2.resize(b->count);
+    b->planes2.resize(b->count);
+    for (int k = 0; k < b->count; ++k) {
+        b->rows2[k] = (int)mem[k].a.fty;
+        b->planes2[k] = (int)mem[k].a.fsz;
+    }
     b->nblocks2 = begin;
     b->lds2 = lds;
     b->uni_nx = uni_nx;
@@ -1298,6 +1305,20 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
     if (block) *block = best_block;
     if (flags) *flags = best_flags;
     if (steps_run) *steps_run = run;
+    return VANSE_OK;
+}
+
+int vanse_batch_two_step_layout(vanse_batch_t b, int count, int *rows, int *planes)
+{
+    if (!b) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_two_step_layout: NULL batch");
+    if (count != b->count || !rows || !planes)
+        return bfail(b, VANSE_EINVAL, "vanse_batch_two_step_layout: count differs from the members or NULL array");
+    if (!b->two_step || !b->fused_ok)
+        return bfail(b, VANSE_ESTATE, "vanse_batch_two_step_layout: no two-step layout in effect");
+    for (int k = 0; k < count; ++k) {
+        rows[k] = b->rows2[k];
+        planes[k] = b->planes2[k];
+    }
     return VANSE_OK;
 }
 

@@ -39,7 +39,7 @@ EXPORTS = [
     "vanse_autotune", "vanse_set_force_field", "vanse_set_fused",
     "vanse_batch_create", "vanse_batch_destroy", "vanse_batch_set_stream",
     "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
-    "vanse_batch_last_error", "vanse_batch_update",
+    "vanse_batch_last_error", "vanse_batch_update", "vanse_batch_two_step_layout",
 ]
 TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT, TUNE_NT_STORES, TUNE_TWO_STEP = 1, 2, 4, 8, 16
 
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
             "vanse_batch_step": (i, [P, i64]),
             "vanse_batch_autotune": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i), I64P]),
             "vanse_batch_last_error": (ctypes.c_char_p, [P]),
+            "vanse_batch_two_step_layout": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "vanse_batch_update": (i, [P, ctypes.POINTER(P), i]),
         }
         for name, (res, args) in sig.items():
@@ -343,6 +344,13 @@ class Batch:
         self._check(self.lib.vanse_batch_autotune(self.h, int(steps_per_trial), ctypes.byref(b),
                                                   ctypes.byref(f), ctypes.byref(n)))
         return b.value, f.value, n.value
+
+    def two_step_layout(self):
+        """[(rows, planes)] per member of the two-step layout in effect."""
+        n = len(self.solvers)
+        rows, planes = (ctypes.c_int * n)(), (ctypes.c_int * n)()
+        self._check(self.lib.vanse_batch_two_step_layout(self.h, n, rows, planes))
+        return list(zip(rows, planes))
 
     def close(self):
         if getattr(self, "h", None):

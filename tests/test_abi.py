@@ -75,6 +75,7 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.vanse_copy_probe(None, None, 16, None) == -1
     assert lib.vanse_set_fused(None, 2, 8) == -1
     assert lib.vanse_autotune(None, 2, None, None, None, None, None, None) == -1
+    assert lib.vanse_batch_two_step_layout(None, 0, None, None) == -1
 
 
 @pytest.mark.parametrize("name,lat_lib,lat_or", [("D2Q9", 0, oracle.D2Q9),

@@ -259,10 +259,16 @@ def test_two_step_batch_24_plane_segments_bitwise(dtype):
     members = [_make_lat("D3Q19", d, t, s, dtype) for d, t, s in cases]
     b = vanse.Batch(members)
     b.set_tuning(256, vanse.TUNE_TWO_STEP, 16)
+    # rows: as many full x-rows as fit 512 interior and 1024 halo-plane cells
+    assert b.two_step_layout() == [(6, 20), (8, 21), (3, 22), (7, 23)]
     b.step(steps)
     for k, s in enumerate(members):
         assert s.time == steps
         assert np.array_equal(s.populations().cpu().numpy(), want[k]), k
+    b.set_tuning(256, 0, 16)
+    with pytest.raises(vanse.VanseError) as e:
+        b.two_step_layout()
+    assert e.value.code == vanse.ESTATE
     b.close()
     for s in members:
         s.close()
