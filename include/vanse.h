@@ -200,9 +200,10 @@ int vanse_batch_set_stream(vanse_batch_t b, void *stream);
  *       with segments of 64 planes, as a single solve would; otherwise each
  *       member gets general tiles (any size) of as many x-rows as fit 512
  *       interior and 1024 (FP64: 512) halo-plane cells per block, and its nz
- *       is split into equal segments of at most 32 planes (at most 24 or 16
- *       when a host-side estimate of the launch finds the batch too small to
- *       fill the GPU with 32).  Every member gets a second population array
+ *       is split into equal segments of at most 32 planes (at most 24, 16,
+ *       12 or 8 when a host-side estimate of the launch finds the batch too
+ *       small to fill the GPU with 32; vanse_batch_two_step_layout reports
+ *       the result).  Every member gets a second population array
  *       (allocated here, kept by the member's solver: its population memory
  *       doubles).  Used for every group of 4 steps of a chunk while all
  *       members sit at even time levels (two launches, so each member ends

@@ -758,11 +758,13 @@ double gen_launch_estimate(const std::vector<const vanse::Solver *> &ms,
     return span;
 }
 
-// Segment target of the general tiles: 32 planes, or 24 or 16 when the
+// Segment target of the general tiles: 32 planes, or 24, 16, 12 or 8 when the
 // estimate above predicts the launch at least 8% faster with them (a batch
 // with too few tiles to fill the chip gains more from extra blocks than it
-// loses to the extra planes of shorter segments; measured on mixed batches of
-// 2-26 M cells, the rule picks the fastest target or one within 3% of it).
+// loses to the extra planes of shorter segments; measured on batches of one
+// to 64 solves and 0.5-26 M cells, the estimate's ratios between targets
+// came within 10% of the measured ones, and the rule picks the fastest
+// target or one within 3% of it).
 int gen_segment_target(const std::vector<const vanse::Solver *> &ms, const std::vector<int> &rows)
 {
     int dev = 0, cus = 256;
@@ -772,7 +774,7 @@ int gen_segment_target(const std::vector<const vanse::Solver *> &ms, const std::
     const double base = gen_launch_estimate(ms, rows, 32, cus);
     int best = 32;
     double best_t = base;
-    for (int target : {24, 16}) {
+    for (int target : {24, 16, 12, 8}) {
         const double t = gen_launch_estimate(ms, rows, target, cus);
         if (t < best_t) {
             best_t = t;
@@ -788,7 +790,7 @@ int gen_segment_target(const std::vector<const vanse::Solver *> &ms, const std::
 // that width divides its ny (batch_uniform_rows), all use that tile with
 // segments of 64 planes, as a single solve would; otherwise each member gets
 // a general tile (batch_fused_rows x-rows) and its nz is split into equal
-// segments of at most 32 planes (24 or 16 for batches too small to fill the
+// segments of at most 32 planes (fewer for batches too small to fill the
 // chip, gen_segment_target).  Leaves fused_ok false (single steps only) when
 // a member has no tile.
 int batch_layout2(vanse_batch *b)

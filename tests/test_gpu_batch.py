@@ -12,7 +12,7 @@ from paper_2208_09267_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 # small enough that the general tiles of the batched two-step launch take
-# 16-plane z-segments (the batch cannot fill the GPU with 32)
+# z-segments of at most 8 planes (the batch cannot fill the GPU with 32)
 CASES = [((17, 13, 11), 0.57, 1), ((32, 32, 32), 0.9, 2), ((48, 40, 36), 0.66, 3),
          ((5, 64, 7), 0.75, 4), ((64, 8, 9), 1.2, 5)]
 
@@ -136,6 +136,8 @@ def test_two_step_batch_matches_solo_bitwise(dtype, steps, chunk):
     members = [_make(d, t, s, dtype, p) for (d, t, s), p in zip(CASES, pre)]
     b = vanse.Batch(members)
     b.set_tuning(128, vanse.TUNE_TWO_STEP, chunk)
+    if dtype != vanse.FP64:
+        assert b.two_step_layout() == [(13, 6), (16, 8), (10, 8), (64, 7), (8, 5)]
     b.step(steps)
     for k, s in enumerate(members):
         assert s.time == pre[k] + steps
@@ -272,3 +274,22 @@ def test_two_step_batch_24_plane_segments_bitwise(dtype):
     b.close()
     for s in members:
         s.close()
+
+
+def test_two_step_batch_single_small_member_8_plane_segments_bitwise():
+    """One 80^3 request alone has 42 general tiles with 32-plane segments;
+    the batched launch gives it 8-plane ones (140 tiles) and it still equals
+    the solve stepped alone."""
+    dtype = vanse.FP32_SHIFTED
+    solo = _make_lat("D3Q19", (80, 80, 80), 0.6, 31, dtype)
+    solo.step(21)
+    want = solo.populations().cpu().numpy()
+    solo.close()
+    m = _make_lat("D3Q19", (80, 80, 80), 0.6, 31, dtype)
+    b = vanse.Batch([m])
+    b.set_tuning(256, vanse.TUNE_TWO_STEP, 16)
+    assert b.two_step_layout() == [(6, 8)]
+    b.step(21)
+    assert np.array_equal(m.populations().cpu().numpy(), want)
+    b.close()
+    m.close()
