@@ -455,7 +455,10 @@ def main():
                     help="comma list; the first one is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched workloads and the served sample")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served sample (a 15 s window of requests at 8/s)")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-d3q27", action="store_true")
     ap.add_argument("--no-single-step", action="store_true",
@@ -582,6 +585,12 @@ def main():
         print("# batched: %s" % json.dumps(out["batched"]), file=sys.stderr, flush=True)
         out["batched_256"] = batched_256_run()
         print("# batched 256^3: %s" % json.dumps(out["batched_256"]), file=sys.stderr, flush=True)
+        if not args.no_serve:
+            # latency of the continuous-batching loop below capacity; the
+            # 10-minute stream at 20/s is `--serve --rate 20 --duration 600`
+            out["served_sample"] = serve_run(8.0, 15.0, args.budget_gb * 1e9, int(args.cell_cap))
+            print("# served sample: %s" % json.dumps(out["served_sample"]), file=sys.stderr,
+                  flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, pert, u0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
