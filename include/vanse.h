@@ -197,7 +197,9 @@ int vanse_batch_set_stream(vanse_batch_t b, void *stream);
  *       vanse_set_fused): when every member has nx = 256 (rows: 4, or 2 in
  *       FP64 or when 4 does not divide ny) or nx = 128 (rows 4, D3Q19) and
  *       those rows divide its ny, all use that compile-time tile
- *       with segments of 64 planes, as a single solve would; otherwise each
+ *       and their nz is split into equal segments of at most 64 planes (at
+ *       most 32, 16 or 8 when a host-side estimate of the launch finds the
+ *       batch too small to fill the GPU with 64); otherwise each
  *       member gets general tiles (any size) of as many x-rows as fit 512
  *       interior and 1024 (FP64: 512) halo-plane cells per block, and its nz
  *       is split into equal segments of at most 32 planes (at most 24, 16,

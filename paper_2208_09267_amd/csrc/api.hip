@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <new>
@@ -720,8 +721,8 @@ int balanced_planes(int nz, int target)
     return (nz + segs - 1) / segs;
 }
 
-// Estimated duration (in cell-planes) of a batched two-step launch of general
-// tiles whose segments aim at `target` planes.  Blocks reach the XCDs in
+// Estimated duration (in cell-planes) of a batched two-step launch whose
+// segments aim at `target` planes.  Blocks reach the XCDs in
 // contiguous ranges of the block index (the kernel's XCD-contiguous order),
 // and within an XCD each block starts on the CU that frees first (one block
 // of the general tile per CU); a block costs its tile's cells per plane times
@@ -758,40 +759,44 @@ double gen_launch_estimate(const std::vector<const vanse::Solver *> &ms,
     return span;
 }
 
-// Segment target of the general tiles: 32 planes, or 24, 16, 12 or 8 when the
-// estimate above predicts the launch at least 8% faster with them (a batch
-// with too few tiles to fill the chip gains more from extra blocks than it
-// loses to the extra planes of shorter segments; measured on batches of one
-// to 64 solves and 0.5-26 M cells, the estimate's ratios between targets
-// came within 10% of the measured ones, and the rule picks the fastest
-// target or one within 3% of it).
-int gen_segment_target(const std::vector<const vanse::Solver *> &ms, const std::vector<int> &rows)
+// Segment target of a batched two-step launch: `base` planes (general tiles
+// 32, compile-time tiles 64), or a shorter one of `shorter` when the estimate
+// above predicts the launch at least 8% faster with it (a batch with too few
+// tiles to fill the chip gains more from extra blocks than it loses to the
+// extra planes of shorter segments).  Measured on general tiles (batches of
+// one to 64 solves, 0.5-26 M cells; the estimate's ratios between targets
+// came within 10% of the measured ones) and on compile-time tiles (one to
+// three 128^3 and one 256^3 solve, FP64/FP32/FP16), the rule picks the
+// fastest target or one within 3% of it.  The estimate counts one block per
+// CU also where two fit: with two, it picked segments too short.
+int segment_target(const std::vector<const vanse::Solver *> &ms, const std::vector<int> &rows,
+                   int base, std::initializer_list<int> shorter)
 {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
         cus = 256;
-    const double base = gen_launch_estimate(ms, rows, 32, cus);
-    int best = 32;
-    double best_t = base;
-    for (int target : {24, 16, 12, 8}) {
+    const double base_t = gen_launch_estimate(ms, rows, base, cus);
+    int best = base;
+    double best_t = base_t;
+    for (int target : shorter) {
         const double t = gen_launch_estimate(ms, rows, target, cus);
         if (t < best_t) {
             best_t = t;
             best = target;
         }
     }
-    return best_t <= base / 1.08 ? best : 32;
+    return best_t <= base_t / 1.08 ? best : base;
 }
 
 // Two-step tables: a tile per member, its second population array
 // (allocated when missing; the member's solver keeps it), and the owner table
 // of that grid.  When every member has the same nx and a compile-time tile of
-// that width divides its ny (batch_uniform_rows), all use that tile with
-// segments of 64 planes, as a single solve would; otherwise each member gets
-// a general tile (batch_fused_rows x-rows) and its nz is split into equal
-// segments of at most 32 planes (fewer for batches too small to fill the
-// chip, gen_segment_target).  Leaves fused_ok false (single steps only) when
+// that width divides its ny (batch_uniform_rows), all use that tile and their
+// nz is split into equal segments of at most 64 planes; otherwise each member
+// gets a general tile (batch_fused_rows x-rows) and segments of at most 32
+// planes.  Batches too small to fill the chip take shorter segments
+// (segment_target).  Leaves fused_ok false (single steps only) when
 // a member has no tile.
 int batch_layout2(vanse_batch *b)
 {
@@ -816,22 +821,21 @@ int batch_layout2(vanse_batch *b)
     auto tile_rows = [&](const Solver &s) {
         return uni_rows ? uni_rows : vanse::batch_fused_rows(s);
     };
-    int gen_target = 32;
-    if (!uni_rows) {
+    int target = 0;
+    {
         std::vector<const Solver *> ms;
         std::vector<int> rows;
         for (int k = 0; k < b->count; ++k) {
             const Solver &s = b->members[k]->s;
-            const int r = vanse::batch_fused_rows(s);
+            const int r = tile_rows(s);
             if (r == 0) return VANSE_OK;  // no tile: single steps only
             ms.push_back(&s);
             rows.push_back(r);
         }
-        gen_target = gen_segment_target(ms, rows);
+        target = uni_rows ? segment_target(ms, rows, 64, {32, 16, 8})
+                          : segment_target(ms, rows, 32, {24, 16, 12, 8});
     }
-    auto tile_planes = [&](const Solver &s) {
-        return uni_rows ? std::min(64, s.geo.nz) : balanced_planes(s.geo.nz, gen_target);
-    };
+    auto tile_planes = [&](const Solver &s) { return balanced_planes(s.geo.nz, target); };
     std::vector<vanse::BatchMember> mem(b->count);
     std::vector<unsigned> owner;
     unsigned begin = 0;

@@ -293,3 +293,23 @@ def test_two_step_batch_single_small_member_8_plane_segments_bitwise():
     assert np.array_equal(m.populations().cpu().numpy(), want)
     b.close()
     m.close()
+
+
+@pytest.mark.parametrize("dtype", [vanse.FP32_SHIFTED, vanse.FP64])
+def test_uniform_batch_of_one_128_cube_takes_shorter_segments_bitwise(dtype):
+    """One 128^3 solve in the batched launch takes the compile-time 128 x 4
+    tile; with 64-plane segments it would have 64 tiles for 256 CUs, so its
+    nz is split into 16-plane segments (256 tiles), and it still equals the
+    solve stepped alone."""
+    solo = _make_lat("D3Q19", (128, 128, 128), 0.6, 41, dtype)
+    solo.step(13)
+    want = solo.populations().cpu().numpy()
+    solo.close()
+    m = _make_lat("D3Q19", (128, 128, 128), 0.6, 41, dtype)
+    b = vanse.Batch([m])
+    b.set_tuning(256, vanse.TUNE_TWO_STEP, 16)
+    assert b.two_step_layout() == [(4, 16)]
+    b.step(13)
+    assert np.array_equal(m.populations().cpu().numpy(), want)
+    b.close()
+    m.close()
