@@ -297,8 +297,8 @@ int vanse_set_fused(vanse_t h, int rows, int planes);
 /* Autotune the launch shape of vanse_step: each candidate (tiled 256-cell
  * row segments with 1, 2 or 4 rows per block where they divide the
  * lattice; flat launches of 256, 512 and 1024 threads; on 3-D lattices the
- * two-step launch of vanse_set_fused with 1, 2, 4 or 8 rows and 8, 32 or
- * 64 planes, and 128 when nz > 64, where its shape exists) runs
+ * two-step launch of vanse_set_fused with 1, 2, 4 or 8 rows and 8, 16, 32
+ * or 64 planes, and 128 when nz > 64, where its shape exists) runs
  * `steps_per_trial` REAL steps timed with HIP events, and the fastest is kept and cached for solves of the same
  * lattice, dtype and size class.  *fused_rows / *fused_planes report the
  * chosen two-step tile (0 / 0: single steps; the tile of the single-step

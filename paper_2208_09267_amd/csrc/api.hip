@@ -517,13 +517,13 @@ int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int
     if (!cached) {
         // single-step candidates: tiled x-row segments of 256 cells with 1, 2, 4
         // rows, and the flattened launch with 256, 512, 1024 threads; then the
-        // two-step launch with 1, 2, 4, 8 rows and 8, 32, 64 planes (and 128
-        // when the lattice has more than 64 planes)
+        // two-step launch with 1, 2, 4, 8 rows and 8, 16, 32, 64 planes (and
+        // 128 when the lattice has more than 64 planes)
         std::vector<SoloChoice> cand = {{256, 1, 0, 0, 0}, {256, 2, 0, 0, 0}, {256, 4, 0, 0, 0},
                                         {256, 1, 1, 0, 0}, {512, 1, 1, 0, 0}, {1024, 1, 1, 0, 0}};
         if (s.d == 3) {
             const int rows[4] = {1, 2, 4, 8};
-            const int planes[4] = {8, 32, 64, 128};
+            const int planes[5] = {8, 16, 32, 64, 128};
             for (int r : rows)
                 for (int p : planes) {
                     if (p > 64 && s.geo.nz <= 64) continue;

@@ -222,10 +222,10 @@ def test_autotune_is_bitwise_neutral_and_counts_its_steps():
         s.set_porosity(0.75, pert, 50.0)
         s.init(None, u0)
     launch = a.autotune(2)
-    # 3 tiled + 3 flat single-step candidates, two-step tiles of 1, 2, 4 rows x 8, 32, 64 planes
-    assert launch.steps_run == 30 and a.time == 30
+    # 3 tiled + 3 flat single-step candidates, two-step tiles of 1, 2, 4 rows x 8, 16, 32, 64 planes
+    assert launch.steps_run == 36 and a.time == 36
     a.step(7)
-    b.step(37)
+    b.step(43)
     assert np.array_equal(a.populations().cpu().numpy(), b.populations().cpu().numpy())
     # same size class again: cached, no steps
     assert b.autotune(2) == launch._replace(steps_run=0)
