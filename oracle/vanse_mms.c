@@ -23,6 +23,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 int oracle_step(int lattice, const int64_t dims[3], double tau, const double *eps,
                 int quad_axes, const double *force, const double *fext,
@@ -311,6 +314,10 @@ int64_t oracle_mms_run_q(int ex, int lattice, int N, double tau, double t_end, i
                         cs[a * N + i] = cos(M_PI * (i * dx - 0.5 * t));
                     }
             }
+            /* cells are independent: the same values in any thread count */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : omp_get_max_threads())
+#endif
             for (cell = 0; cell < ncells; ++cell) {
                 const int64_t x = cell % dims[0], y = (cell / dims[0]) % dims[1],
                               z = cell / (dims[0] * dims[1]);
