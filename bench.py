@@ -387,8 +387,14 @@ def serve_run(rate, duration, budget, cell_cap, seed=4):
     results = srv.run(arrivals)
     wall = time.perf_counter() - t0
     out = serve.summarize(results, wall)
+    lups = srv.stats["lups_two_step_tuning"] + srv.stats["lups_single_step_tuning"]
+    stepping = lups / srv.time["step"] / 1e9 if srv.time["step"] > 0 else float("nan")
     out.update({"rate_per_s": rate, "arrival_window_s": duration,
-                "offered_glups": offered / 1e9, "hbm_budget_gb": budget / 1e9,
+                "offered_glups": offered / 1e9,
+                # lattice updates per second while the batch steps: the capacity
+                "stepping_glups": stepping, "offered_over_capacity": offered / 1e9 / stepping,
+                "latency": "arrival -> moments (rho, p, u, FP64) copied into host memory",
+                "hbm_budget_gb": budget / 1e9,
                 "cell_cap": cell_cap, "batch_rebuilds": srv.stats["rebuilds"],
                 "chunks": srv.stats["chunks"],
                 "batch_steps_by_tuning": {"two_step": srv.stats["steps_two_step_tuning"],
@@ -424,26 +430,74 @@ def copy_probe(nbytes=1 << 30, reps=10):
             "frac_hbm": round(2 * nbytes / (ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4)}
 
 
-def cpu_baseline(w, pert, u0, seconds):
-    """The CPU oracle (FP64, as it stands) on the same workload, timed for a
-    bounded number of steps."""
+def _cpu_model():
+    """Host CPU model name (from /proc/cpuinfo) and logical core count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def _oracle_rate(w, pert, u0, seconds, threads, min_steps=2, max_steps=None):
+    """Steps of workload w on the CPU oracle (FP64, as it stands) until
+    `seconds` have passed (at least min_steps, at most max_steps): (MLUPS,
+    steps, seconds)."""
     import oracle
 
-    lat = oracle.D3Q19
+    lat = {"D2Q9": oracle.D2Q9, "D3Q19": oracle.D3Q19}[w.lattice]
     eps0 = oracle.eps_at(w.dims, w.eps_mean, pert, w.period, 0)
     f = oracle.init(lat, w.dims, eps0, None, u0)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     steps, elapsed = 0, 0.0
-    while elapsed < seconds or steps < 2:
+    while (elapsed < seconds or steps < min_steps) and (max_steps is None or steps < max_steps):
+        k = 1 if w.ncells > 100000 else 50
+        if max_steps is not None:
+            k = min(k, max_steps - steps)
         t0 = time.perf_counter()
-        f, _ = oracle.run_separable(lat, w.dims, w.tau, w.eps_mean, pert, w.period, f, steps, 1,
-                                    fext=w.force, nthreads=threads)
+        f, _ = oracle.run_separable(lat, w.dims, w.tau, w.eps_mean, pert, w.period, f, steps, k,
+                                    quad_axes=w.quad_axes, fext=w.force, nthreads=threads)
         elapsed += time.perf_counter() - t0
-        steps += 1
-    return {"value": w.ncells * steps / elapsed / 1e6, "unit": "MLUPS", "cores": threads,
-            "kind": "oracle",
+        steps += k
+    return w.ncells * steps / elapsed / 1e6, steps, elapsed
+
+
+def cpu_baseline(w, pert, u0, seconds, full=False):
+    """The CPU oracle (FP64, as it stands) on the host cores: the headline
+    workload for a bounded number of steps on every core and on one core,
+    the 64^2 D2Q9 workload in full (1000 steps) and a bounded sample of the
+    128^3 workload (all of its 1000 steps with full=True)."""
+    from paper_2208_09267_amd import workloads as W
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    model, ncpu = _cpu_model()
+    rate, steps, el = _oracle_rate(w, pert, u0, seconds, threads)
+    rate1, steps1, el1 = _oracle_rate(w, pert, u0, seconds / 3, 1, min_steps=1)
+    w0 = W.d2q9_64()
+    r0, s0, e0 = _oracle_rate(w0, w0.eps_pert(), None, 0.0, threads, max_steps=w0.steps,
+                              min_steps=w0.steps)
+    w1 = W.d3q19_128()
+    if full:
+        r1, s1, e1 = _oracle_rate(w1, w1.eps_pert(), w1.u0(), 0.0, threads,
+                                  min_steps=w1.steps, max_steps=w1.steps)
+    else:
+        r1, s1, e1 = _oracle_rate(w1, w1.eps_pert(), w1.u0(), seconds / 3, threads)
+    return {"value": rate, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": "%d steps of the full %dx%dx%d D3Q19 FP64 workload (%.1f s)"
-                      % (steps, w.dims[0], w.dims[1], w.dims[2], elapsed)}
+                      % (steps, w.dims[0], w.dims[1], w.dims[2], el),
+            "host_cpu": model, "host_logical_cpus": ncpu,
+            "one_thread": {"value": rate1, "unit": "MLUPS", "cores": 1,
+                           "sample": "%d steps of the same workload (%.1f s)" % (steps1, el1)},
+            "d2q9_64": {"value": r0, "unit": "MLUPS", "cores": threads,
+                        "sample": "the full workload: %d steps of D2Q9 64^2 FP64 (%.2f s)"
+                                  % (s0, e0)},
+            "d3q19_128": {"value": r1, "unit": "MLUPS", "cores": threads,
+                          "sample": "%d%s steps of D3Q19 128^3 FP64 (%.1f s)"
+                                    % (s1, " (all)" if full else "", e1)}}
 
 
 def main():
@@ -455,6 +509,10 @@ def main():
                     help="comma list; the first one is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="time all 1000 steps of the 128^3 workload on the CPU oracle")
+    ap.add_argument("--cpu-only", action="store_true",
+                    help="only the CPU oracle timings (no GPU)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched workloads and the served sample")
     ap.add_argument("--no-serve", action="store_true",
@@ -501,6 +559,10 @@ def main():
     w = W.d3q19_256()
     pert = w.eps_pert()
     u0 = w.u0()
+    if args.cpu_only:
+        print(json.dumps({"cpu_baseline": cpu_baseline(w, pert, u0, args.cpu_seconds,
+                                                       args.cpu_full)}), flush=True)
+        return
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     pert_t = torch.from_numpy(pert).to(dev)
@@ -562,7 +624,15 @@ def main():
                      "lups_per_launch": w.ncells * r["steps_per_launch"],
                      "bytes_per_lup": r["bytes_per_lup"],
                      "effective_gb_s_single_step_bytes": round(r["effective_gb_s"], 1),
-                     "effective_frac_single_step_bytes": round(r["effective_frac"], 4)},
+                     "effective_frac_single_step_bytes": round(r["effective_frac"], 4),
+                     "single_pass_bytes_per_lup": BYTES_PER_PASS[head],
+                     "note": "achieved/frac: the kernel's own algorithmic bytes per launch "
+                             "(populations read and written once, one phi value, per cell and "
+                             "launch) over its HIP-event launch time; a two-step launch does two "
+                             "lattice updates per cell for them.  effective_*_single_step_bytes "
+                             "count single_pass_bytes_per_lup per lattice update, which assumes "
+                             "one HBM pass per step: the bandwidth a one-step-per-pass kernel "
+                             "would need for the same MLUPS (it can exceed the peak)."},
         "variants": {v: {"mlups": round(x["mlups"], 1), "ms_per_step": round(x["ms_per_step"], 5),
                          "kernel": x["kernel"], "ms_per_launch": round(x["ms_per_launch"], 5),
                          "gb_s": round(x["gb_s"], 1), "frac_hbm": round(x["frac_hbm"], 4),
@@ -586,13 +656,19 @@ def main():
         out["batched_256"] = batched_256_run()
         print("# batched 256^3: %s" % json.dumps(out["batched_256"]), file=sys.stderr, flush=True)
         if not args.no_serve:
-            # latency of the continuous-batching loop below capacity; the
-            # 10-minute stream at 20/s is `--serve --rate 20 --duration 600`
-            out["served_sample"] = serve_run(8.0, 15.0, args.budget_gb * 1e9, int(args.cell_cap))
-            print("# served sample: %s" % json.dumps(out["served_sample"]), file=sys.stderr,
-                  flush=True)
+            # the served workload's arrival rate (20 requests/s) over a 30 s
+            # window of arrivals: offered load above capacity, so latency is
+            # queueing; the 10-minute stream is `--serve --rate 20 --duration
+            # 600`.  Then 8 requests/s (below capacity) for the latency of
+            # the loop itself.
+            out["served"] = serve_run(20.0, 30.0, args.budget_gb * 1e9, int(args.cell_cap))
+            print("# served: %s" % json.dumps(out["served"]), file=sys.stderr, flush=True)
+            out["served_below_capacity"] = serve_run(8.0, 15.0, args.budget_gb * 1e9,
+                                                     int(args.cell_cap))
+            print("# served below capacity: %s" % json.dumps(out["served_below_capacity"]),
+                  file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, pert, u0, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, pert, u0, args.cpu_seconds, args.cpu_full)
     print(json.dumps(out), flush=True)
 
 

@@ -99,7 +99,9 @@ int vanse_set_stream(vanse_t h, void *stream);
  *              paper, diagonals excluded); 0 selects all d axes;
  *              VANSE_QUAD_NONE drops the correction (I = phi)
  * Validates on the device that phi stays in (0, 1] for every reachable m and
- * that eps_pert is finite; synchronises.  Errors: EINVAL, EDEVICE. */
+ * that eps_pert is finite before anything is copied; synchronises.  A
+ * rejected call leaves the solver as it was (its previous phi, if any, stays
+ * in effect).  Errors: EINVAL, EDEVICE. */
 int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, double period,
                        int quad_axes);
 
@@ -112,7 +114,9 @@ int vanse_set_force(vanse_t h, const double F[3]);
  * solution forces; sum_k F_k of the Guo forcing term), added to F_ext and to
  * the pressure-correction force.  F: device FP64 SoA [d][ncells], copied
  * (to FP32 in the reduced modes; the first call allocates d planes);
- * NULL switches the field off.  Asynchronous.  Errors: ENOMEM, EDEVICE. */
+ * NULL switches the field off.  Validates on the device that every value is
+ * finite before anything is copied, and synchronises; a rejected call leaves
+ * the solver as it was.  Errors: EINVAL, ENOMEM, EDEVICE. */
 int vanse_set_force_field(vanse_t h, const double *F);
 
 /* Initial populations (eq. equilibrium): f_i = f_i^eq of M0 = rho0 phi(x, 0)
@@ -173,7 +177,10 @@ typedef struct vanse_batch *vanse_batch_t;
  * they must outlive it.  A member may also be stepped alone between batch
  * calls, in stream order with the batch: the batch follows its time level
  * and, after two-step launches, its current population array (the batch
- * then rebuilds its tables once, synchronising its stream).  Allocates
+ * then rebuilds its tables once, synchronising its stream).  A member's
+ * vanse_set_porosity, vanse_set_force or vanse_set_force_field after the
+ * batch was built takes effect at the next batch call, which rebuilds the
+ * tables the same way.  Allocates
  * small device tables (hipMalloc).  Errors: EINVAL, ESTATE, ENOMEM,
  * EDEVICE. */
 int vanse_batch_create(const vanse_t *solvers, int count, vanse_batch_t *out);

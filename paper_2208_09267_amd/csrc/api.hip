@@ -27,6 +27,7 @@ struct vanse_solver {
 struct vanse_batch {
     std::vector<vanse_t> members;
     std::vector<void *> layout_f;       // members' population arrays in the member table
+    std::vector<unsigned long long> layout_gen;  // members' parameter generations in the tables
     int lattice = 0, mode = 0, count = 0;
     int block = 256;
     bool nt = false;
@@ -141,6 +142,31 @@ size_t elem_bytes(int mode)
     return mode == vanse::MODE_F64 ? 8 : (mode == vanse::MODE_F32S ? 4 : 2);
 }
 
+// min, max and number of non-finite values of n caller-provided FP64 values
+// (device), through the solver's reduction scratch; synchronises its stream.
+hipError_t check_range(Solver &s, const double *src, long long n, double *lo, double *hi,
+                       double *bad)
+{
+    static thread_local double host[3 * vanse::kReduceBlocks];
+    hipError_t e = vanse::launch_range(src, n, s.scratch, s.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, s.scratch, sizeof(double) * 3 * vanse::kReduceBlocks,
+                           hipMemcpyDeviceToHost, s.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+    if (e != hipSuccess) return e;
+    double l = 1e300, u = -1e300, b = 0.0;
+    for (int k = 0; k < vanse::kReduceBlocks; ++k) {
+        l = std::fmin(l, host[3 * k]);
+        u = std::fmax(u, host[3 * k + 1]);
+        b += host[3 * k + 2];
+    }
+    if (l > u) l = u = 0.0;  // no finite value
+    *lo = l;
+    *hi = u;
+    *bad = b;
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -231,33 +257,15 @@ int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, doubl
     if (quad_axes != VANSE_QUAD_NONE && (quad_axes < 0 || quad_axes > 7 || (s.d == 2 && (quad_axes & 4))))
         return fail(&s, VANSE_EINVAL, "vanse_set_porosity: bad quad_axes mask");
     hipError_t e;
+    // range of the caller's perturbation, checked before anything is taken
+    // over: a rejected call leaves the solver exactly as it was
+    double lo = 0.0, hi = 0.0;
     if (eps_pert) {
-        if (s.mode == vanse::MODE_F64)
-            e = hipMemcpyAsync(s.pert, eps_pert, sizeof(double) * s.geo.ncells,
-                               hipMemcpyDeviceToDevice, s.stream);
-        else
-            e = vanse::launch_convert_pert(s, eps_pert);
-    } else {
-        e = hipMemsetAsync(s.pert, 0, s.pert_bytes, s.stream);
+        double bad = 0.0;
+        if ((e = check_range(s, eps_pert, s.geo.ncells, &lo, &hi, &bad)) != hipSuccess)
+            return hip_fail(&s, e, "vanse_set_porosity");
+        if (bad > 0.0) return fail(&s, VANSE_EINVAL, "vanse_set_porosity: eps_pert is not finite");
     }
-    if (e != hipSuccess) return hip_fail(&s, e, "vanse_set_porosity");
-    // range check of the stored perturbation on the device
-    double *partials = s.scratch;
-    if ((e = vanse::launch_pert_range(s, partials)) != hipSuccess)
-        return hip_fail(&s, e, "vanse_set_porosity");
-    static thread_local double host[3 * vanse::kReduceBlocks];
-    if ((e = hipMemcpyAsync(host, partials, sizeof(double) * 3 * vanse::kReduceBlocks,
-                            hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(s.stream)) != hipSuccess)
-        return hip_fail(&s, e, "vanse_set_porosity");
-    double lo = 1e300, hi = -1e300, bad = 0.0;
-    for (int b = 0; b < vanse::kReduceBlocks; ++b) {
-        lo = std::fmin(lo, host[3 * b]);
-        hi = std::fmax(hi, host[3 * b + 1]);
-        bad += host[3 * b + 2];
-    }
-    if (bad > 0.0) return fail(&s, VANSE_EINVAL, "vanse_set_porosity: eps_pert is not finite");
-    if (lo > hi) lo = hi = 0.0;
     // reachable range of phi = eps_mean + m pert: m in [-1, 1] if periodic, else m = 1
     double pmin, pmax;
     if (period > 0.0) {
@@ -275,10 +283,21 @@ int vanse_set_porosity(vanse_t h, double eps_mean, const double *eps_pert, doubl
                       pmin, pmax);
         return fail(&s, VANSE_EINVAL, buf);
     }
+    if (eps_pert) {
+        if (s.mode == vanse::MODE_F64)
+            e = hipMemcpyAsync(s.pert, eps_pert, sizeof(double) * s.geo.ncells,
+                               hipMemcpyDeviceToDevice, s.stream);
+        else
+            e = vanse::launch_convert_pert(s, eps_pert);
+    } else {
+        e = hipMemsetAsync(s.pert, 0, s.pert_bytes, s.stream);
+    }
+    if (e != hipSuccess) return hip_fail(&s, e, "vanse_set_porosity");
     s.eps_mean = eps_mean;
     s.period = period;
     s.qmask = quad_axes == 0 ? (s.d == 2 ? 3 : 7) : (quad_axes == VANSE_QUAD_NONE ? 0 : quad_axes);
     s.porosity_set = true;
+    ++s.gen;
     return VANSE_OK;
 }
 
@@ -293,6 +312,7 @@ int vanse_set_force(vanse_t h, const double F[3])
             return fail(&s, VANSE_EINVAL, "vanse_set_force: z force on a 2-D lattice");
     }
     for (int a = 0; a < 3; ++a) s.F[a] = F[a];
+    ++s.gen;
     return VANSE_OK;
 }
 
@@ -302,14 +322,22 @@ int vanse_set_force_field(vanse_t h, const double *F)
     Solver &s = h->s;
     if (!F) {
         s.force_on = false;
+        ++s.gen;
         return VANSE_OK;
     }
-    const size_t elem = s.mode == vanse::MODE_F64 ? 8 : 4;
     hipError_t e;
+    {
+        double lo, hi, bad = 0.0;
+        if ((e = check_range(s, F, (long long)s.d * s.geo.ncells, &lo, &hi, &bad)) != hipSuccess)
+            return hip_fail(&s, e, "vanse_set_force_field");
+        if (bad > 0.0) return fail(&s, VANSE_EINVAL, "vanse_set_force_field: F is not finite");
+    }
+    const size_t elem = s.mode == vanse::MODE_F64 ? 8 : 4;
     if (!s.force) {
         s.force_bytes = (size_t)s.d * (size_t)s.geo.stride * elem;
         if ((e = hipMalloc(&s.force, s.force_bytes)) != hipSuccess) {
             s.force = nullptr;
+            s.force_bytes = 0;
             (void)hipGetLastError();
             return fail(&s, VANSE_ENOMEM, std::string("vanse_set_force_field: ") + hipGetErrorString(e));
         }
@@ -325,6 +353,7 @@ int vanse_set_force_field(vanse_t h, const double *F)
         if (e != hipSuccess) return hip_fail(&s, e, "vanse_set_force_field");
     }
     s.force_on = true;
+    ++s.gen;
     return VANSE_OK;
 }
 
@@ -919,9 +948,11 @@ int batch_layout(vanse_batch *b)
     std::vector<unsigned> owner;
     unsigned begin = 0;
     b->layout_f.assign(b->count, nullptr);
+    b->layout_gen.assign(b->count, 0);
     for (int k = 0; k < b->count; ++k) {
         const Solver &s = b->members[k]->s;
         b->layout_f[k] = s.f;
+        b->layout_gen[k] = s.gen;
         vanse::BatchMember &m = mem[k];
         m.a = vanse::step_args(s, s.t);
         m.a.block = (unsigned)b->block;
@@ -1047,10 +1078,11 @@ int batch_run(vanse_batch *b, int64_t n, bool allow_graph)
     for (int k = 0; k < b->count; ++k) {
         const Solver &s = b->members[k]->s;
         if (s.unstable) return bfail(b, VANSE_EUNSTABLE, "vanse_batch_step: a member is unstable");
-        moved = moved || s.f != b->layout_f[k];
+        moved = moved || s.f != b->layout_f[k] || s.gen != b->layout_gen[k];
         if (b->two_step && b->fused_ok) moved = moved || s.f_alt != b->layout_f2[k];
     }
-    if (moved) {  // a member switched or freed population arrays since the layout
+    if (moved) {  // a member switched or freed population arrays, or changed its
+                  // phi or forces, since the layout
         hipError_t e = hipStreamSynchronize(b->stream);
         if (e != hipSuccess) return bfail(b, VANSE_EDEVICE, std::string("vanse_batch_step: ") + hipGetErrorString(e));
         int rc = batch_layout(b);

@@ -85,6 +85,9 @@ struct Solver {
     int qmask = 0;
     double F[3] = {0.0, 0.0, 0.0};
     bool porosity_set = false, initialized = false, unstable = false;
+    // bumped by every setter of the step's physics (phi, forces), so that a
+    // batch knows when its copy of the step parameters is stale
+    unsigned long long gen = 0;
     int64_t t = 0;
     int tile_x = 256;            // step kernel tile: x-row segment per block
     int tile_y = 1;              //   and rows per block
@@ -186,7 +189,9 @@ hipError_t launch_populations(const Solver &s, int parity, double *f);
 hipError_t launch_diagnostics(const Solver &s, int parity, double m, double *out_dev);
 hipError_t launch_convert_pert(const Solver &s, const double *src);
 hipError_t launch_convert(const double *src, float *dst, long long n, hipStream_t st);
-hipError_t launch_pert_range(const Solver &s, double *out_dev);
+// min, max and non-finite count of n FP64 values: per-block triples in
+// partials[3 * kReduceBlocks]
+hipError_t launch_range(const double *src, long long n, double *partials, hipStream_t st);
 hipError_t launch_copy_probe(void *dst, const void *src, int64_t bytes, hipStream_t st);
 
 }  // namespace vanse

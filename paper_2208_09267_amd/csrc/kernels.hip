@@ -998,16 +998,16 @@ __global__ void __launch_bounds__(kReduceThreads) finalize_kernel(const double *
     block_reduce<NV>(acc, out);
 }
 
-// min, max and non-finite count of the stored phi perturbation.
-template <class R>
-__global__ void __launch_bounds__(kReduceThreads) pert_range_kernel(const R *__restrict__ pert,
-                                                                    int n,
-                                                                    double *__restrict__ partials)
+// min, max and non-finite count of n FP64 values (a caller's input array,
+// checked before the library takes it over).
+__global__ void __launch_bounds__(kReduceThreads) range_kernel(const double *__restrict__ src,
+                                                               long long n,
+                                                               double *__restrict__ partials)
 {
     double lo = 1e300, hi = -1e300, bad = 0.0;
-    for (int c = blockIdx.x * kReduceThreads + threadIdx.x; c < n;
-         c += gridDim.x * kReduceThreads) {
-        const double v = pert[c];
+    for (long long c = (long long)blockIdx.x * kReduceThreads + threadIdx.x; c < n;
+         c += (long long)gridDim.x * kReduceThreads) {
+        const double v = src[c];
         if (!isfinite(v)) {
             bad += 1.0;
         } else {
@@ -1417,14 +1417,9 @@ hipError_t launch_convert(const double *src, float *dst, long long n, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_pert_range(const Solver &s, double *out_dev)
+hipError_t launch_range(const double *src, long long n, double *partials, hipStream_t st)
 {
-    if (s.mode == MODE_F64)
-        pert_range_kernel<double><<<kReduceBlocks, kReduceThreads, 0, s.stream>>>(
-            static_cast<const double *>(s.pert), s.geo.ncells, out_dev);
-    else
-        pert_range_kernel<float><<<kReduceBlocks, kReduceThreads, 0, s.stream>>>(
-            static_cast<const float *>(s.pert), s.geo.ncells, out_dev);
+    range_kernel<<<kReduceBlocks, kReduceThreads, 0, st>>>(src, n, partials);
     return hipGetLastError();
 }
 

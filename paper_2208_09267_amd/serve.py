@@ -16,7 +16,10 @@ while others are on the GPU therefore overlap with them on the device.
 Because the per-cell arithmetic of the batched launch does not depend on
 the other members, every result is bitwise identical alone and in the mix.
 
-Latency = time the moments reach host memory - arrival time.
+Latency = arrival time -> the time the solve's moments (rho, p, u in FP64)
+have been copied into host memory.  The copy goes to a pinned staging buffer
+that the loop reuses; keep_fields=True also hands each result its own numpy
+arrays.
 """
 from __future__ import annotations
 
@@ -158,6 +161,25 @@ class Server:
         # default batched launch, and the autotuned one per size class
         self.tuning = (256, vanse.TUNE_TWO_STEP if two_step else 0)
         self._tuned = {}
+        self._host = torch.empty(0, dtype=torch.float64)  # pinned staging of the moments
+
+    def _to_host(self, solver) -> Tuple[np.ndarray, ...]:
+        """Copy the solve's moments into the pinned staging buffer (grown
+        when needed, then reused) and wait for the copy.  Returns (rho, p, u)
+        views into that buffer, valid until the next call."""
+        fields = solver.moments()
+        total = sum(t.numel() for t in fields)
+        if self._host.numel() < total:
+            self._host = torch.empty(max(total, self._host.numel() * 3 // 2),
+                                     dtype=torch.float64, pin_memory=True)
+        views, off = [], 0
+        for t in fields:
+            dst = self._host[off:off + t.numel()].view(t.shape)
+            dst.copy_(t, non_blocking=True)
+            views.append(dst)
+            off += t.numel()
+        torch.cuda.current_stream().synchronize()
+        return tuple(v.numpy() for v in views)
 
     def _bytes(self, work: W.Workload) -> int:
         return state_bytes(work.lattice, work.dims, self.dtype, self.two_step)
@@ -296,13 +318,10 @@ class Server:
                 # update, but it is not stepped before that
                 dirty = True
                 for a in done:
-                    rho, p, u = a.solver.moments()
+                    rho, p, u = self._to_host(a.solver)
+                    a.result.finish = clock() - t0   # its moments are in host memory
                     if self.keep_fields:
-                        a.result.rho, a.result.p, a.result.u = (rho.cpu().numpy(), p.cpu().numpy(),
-                                                                u.cpu().numpy())
-                    else:
-                        torch.cuda.current_stream().synchronize()
-                    a.result.finish = clock() - t0
+                        a.result.rho, a.result.p, a.result.u = rho.copy(), p.copy(), u.copy()
                     results[a.rid] = a.result
                     used -= self._bytes(a.work)
                     a.solver.close()

@@ -82,6 +82,10 @@ SHAPES = [("D3Q19", (64, 8, 6), 1, 4), ("D3Q19", (64, 8, 6), 2, 32), ("D3Q19", (
           ("D3Q19", (64, 8, 6), 8, 3), ("D3Q19", (128, 4, 5), 2, 2), ("D3Q19", (64, 2, 1), 2, 8),
           ("D3Q19", (64, 1, 2), 1, 1), ("D3Q19", (192, 6, 7), 3, 5), ("D3Q19", (256, 4, 9), 4, 4),
           ("D3Q19", (128, 12, 3), 6, 2),
+          # the compile-time tiles of the benchmarked launches: 128 x 4 (the
+          # 128^3 workload, 16-plane segments) and 256 x 2 (FP64 at 256^3,
+          # 128-plane segments, here with a 2-plane last segment)
+          ("D3Q19", (128, 8, 20), 4, 16), ("D3Q19", (256, 4, 130), 2, 128),
           ("D3Q27", (64, 4, 5), 2, 2), ("D3Q27", (64, 8, 6), 8, 4), ("D3Q27", (128, 6, 4), 3, 3),
           ("D3Q27", (64, 3, 1), 3, 1), ("D3Q27", (256, 4, 5), 4, 3), ("D3Q27", (256, 8, 3), 4, 2),
           # general tiles: nx not a multiple of 64, rows not dividing ny (shorter last tile)

@@ -93,26 +93,42 @@ def test_d3q19_ragged_grid_vs_oracle():
     assert rel_linf(u, u_o) <= 1e-12
 
 
-def test_d3q19_128_full_run_vs_oracle_samples():
+def _sampled_errors(g, rho, p, u):
+    """Relative Linf errors at the oracle's sampled cells, normalised by the
+    oracle's full-field Linf norms; p also by the stricter |p - mean p|."""
+    cells = g["cells"]
+    dp = np.abs(p[cells] - g["p"]).max()
+    return (np.abs(rho[cells] - g["rho"]).max() / g["norms"][0], dp / g["norms"][1],
+            np.abs(u[:, cells] - g["u"]).max() / g["norms"][2], dp / g["norms"][3])
+
+
+@pytest.mark.parametrize("fused", [None, (4, 16)])
+def test_d3q19_128_full_run_vs_oracle_samples(fused):
+    """The 128^3 workload after 1000 steps, in the single-step kernel and in
+    the launch the benchmark times (two-step, the compile-time 128 x 4 tile
+    with 16-plane segments: every step of the run)."""
     path = os.path.join(GOLD, "d3q19_128.npz")
-    if not os.path.exists(path):
-        pytest.skip("oracle reference d3q19_128.npz not generated")
     g = np.load(path)
     w = W.d3q19_128()
-    s, rho, p, u = gpu_run(w.lattice, w.dims, w.tau, w.eps_mean, w.eps_pert(), w.period,
-                           w.steps, u0=w.u0())
+    s = vanse.Solver(w.lattice, w.dims, w.tau, vanse.FP64)
+    s.set_porosity(w.eps_mean, torch.from_numpy(w.eps_pert()).cuda(), w.period)
+    s.init(None, torch.from_numpy(np.ascontiguousarray(w.u0())).cuda())
+    if fused:
+        s.set_fused(*fused)
+    s.step(w.steps)
+    assert s.time == w.steps
+    rho, p, u = (t.cpu().numpy() for t in s.moments())
     mass = s.diagnostics()[0]
     s.close()
-    cells = g["cells"]
-    e_rho = np.abs(rho[cells] - g["rho"]).max() / g["norms"][0]
-    e_p = np.abs(p[cells] - g["p"]).max() / g["norms"][1]
-    e_u = np.abs(u[:, cells] - g["u"]).max() / g["norms"][2]
-    print("sampled rel Linf rho %.3e p %.3e u %.3e" % (e_rho, e_p, e_u))
+    e_rho, e_p, e_u, e_pm = _sampled_errors(g, rho, p, u)
+    print("sampled rel Linf rho %.3e p %.3e u %.3e (p mean-free %.3e)" % (e_rho, e_p, e_u, e_pm))
     assert e_rho <= 1e-11 and e_p <= 1e-11 and e_u <= 1e-11
+    assert e_pm <= 1e-9
     assert abs(mass - float(g["mass"])) <= 1e-12 * abs(float(g["mass"]))
     # full-field properties that hold at any size
     assert np.abs(u).max() == pytest.approx(g["norms"][2], rel=1e-9)
     assert np.abs(p).max() == pytest.approx(g["norms"][1], rel=1e-12)
+    assert np.abs(p - p.mean()).max() == pytest.approx(g["norms"][3], rel=1e-8)
 
 
 def test_mass_conserved_and_momentum_gains_force():
@@ -233,34 +249,48 @@ def test_autotune_is_bitwise_neutral_and_counts_its_steps():
     b.close()
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED])
-def test_d3q19_256_full_run_in_bench_launch_vs_oracle_samples(dtype):
-    """The headline workload (256^3, 2000 steps) in the launch shape the
-    benchmark uses (autotuned during warm-up), against oracle samples:
-    FP64 to 1e-11 relative; FP32 shifted within its storage error."""
-    path = os.path.join(GOLD, "d3q19_256.npz")
-    if not os.path.exists(path):
-        pytest.skip("oracle reference d3q19_256.npz not generated")
-    g = np.load(path)
+# (storage, two-step rows, planes, tolerances on rho, p, u and on p against
+# the stricter scale |p - mean p|).  FP64: the 1e-11 bar.  The reduced
+# modes: twice their recorded full-field errors against FP64 after 2000
+# steps (FP32 shifted: 2.0e-5 / 6.7e-6 / 7.4e-7 absolute, i.e. 2.0e-5 /
+# 2.0e-5 / 3.7e-5 relative to the norms and 3.5e-3 of the pressure
+# deviation scale 0.0019, almost all of it the uniform mass-rounding drift;
+# FP16 shifted: 7.4e-4 / 2.5e-4 / 4.0e-4 absolute, i.e. 7e-4 / 7e-4 / 2.3e-2
+# relative and 0.13 of the deviation scale).
+BENCH_256 = [(vanse.FP64, 2, 128, (1e-11, 1e-11, 1e-11, 1e-9)),
+             (vanse.FP32_SHIFTED, 4, 64, (4e-5, 4e-5, 1e-4, 7e-3)),
+             (vanse.FP16_SHIFTED, 4, 64, (1.5e-3, 1.5e-3, 5e-2, 0.3))]
+
+
+@pytest.mark.parametrize("dtype,rows,planes,tol", BENCH_256)
+def test_d3q19_256_full_run_in_bench_launch_vs_oracle_samples(dtype, rows, planes, tol):
+    """The headline workload (256^3, 2000 steps), every step in the two-step
+    launch the benchmark times (the shapes of its recorded launch table:
+    FP32/FP16 256 x 4 tiles in 1024-thread blocks with 64-plane segments,
+    FP64 256 x 2 tiles with 128-plane segments), against the oracle's
+    sampled cells."""
+    import bench
+
+    name = {vanse.FP64: "fp64", vanse.FP32_SHIFTED: "fp32_shifted",
+            vanse.FP16_SHIFTED: "fp16_shifted"}[dtype]
+    assert bench.FIXED_LAUNCH[name][3:] == (rows, planes)
+    label = bench.kernel_name(name, rows)
+    assert label == "fused2_kernel<D3Q19, %s, rows %d>" % (bench.MODE_NAME[name], rows)
+    g = np.load(os.path.join(GOLD, "d3q19_256.npz"))
     w = W.d3q19_256()
     s = vanse.Solver(w.lattice, w.dims, w.tau, dtype)
     s.set_porosity(w.eps_mean, torch.from_numpy(w.eps_pert()).cuda(), w.period)
     s.init(None, torch.from_numpy(np.ascontiguousarray(w.u0())).cuda())
-    launch = s.autotune(4)
-    print("launch", launch)
-    s.step(w.steps - launch.steps_run)
+    s.set_fused(rows, planes)
+    s.step(w.steps)     # t = 0 and 2000 steps: every step in a two-step launch
     assert s.time == w.steps
     rho, p, u = (t.cpu().numpy() for t in s.moments())
     s.close()
-    cells = g["cells"]
-    e_rho = np.abs(rho[cells] - g["rho"]).max() / g["norms"][0]
-    e_p = np.abs(p[cells] - g["p"]).max() / g["norms"][1]
-    e_u = np.abs(u[:, cells] - g["u"]).max() / g["norms"][2]
-    print("256^3 sampled rel Linf rho %.3e p %.3e u %.3e" % (e_rho, e_p, e_u))
-    if dtype == vanse.FP64:
-        assert e_rho <= 1e-11 and e_p <= 1e-11 and e_u <= 1e-11
-    else:
-        assert e_rho <= 1e-4 and e_p <= 1e-4 and e_u <= 1e-4
+    errs = _sampled_errors(g, rho, p, u)
+    print("%s 256^3 sampled rel Linf rho %.3e p %.3e u %.3e (p mean-free %.3e)"
+          % ((label,) + errs))
+    for e, t, what in zip(errs, tol, ("rho", "p", "u", "p mean-free")):
+        assert e <= t, (what, e, t)
 
 
 def test_largest_grid_equals_replicated_row_bitwise():
