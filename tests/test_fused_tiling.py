@@ -14,7 +14,15 @@ compile-time ones -- and checks, as the kernel computes them:
 * the LDS phi ring of 5 planes: every read finds the plane it wants in its
   slot, written before the barrier that precedes the read;
 * each destination slot of the output array is written by exactly one owning
-  thread over the launch.
+  thread over the launch;
+* the halo-wave skip (a wave collides and pushes only if its first lane is a
+  real halo cell, or a compile-time constant says the whole halo slot is
+  real): no real halo cell sits in a skipped wave, every slab slot is
+  written by a computing wave, and a computing lane past the tile repeats a
+  cell that its real lane computes in the same phase.  Nothing computed
+  inside the skipped branch is carried to a later iteration (the next
+  plane's loads are issued before it), so a skipped wave changes no value
+  that is read.
 
 The emulation restates the kernel's index arithmetic in numpy; it shares no
 code with the HIP source.
@@ -30,7 +38,10 @@ D3Q27 = [(0,0,0)] + [c for c in itertools.product((-1,0,1), repeat=3) if c != (0
 D3Q27 = D3Q27 + [tuple(-v for v in c) for c in D3Q27[1:]]
 
 
-def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
+def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
+    """TXMAX: the x-split general tiles of the batched launch (tiles of
+    TXMAX interior columns, a shorter last one, plus a halo column on each
+    side); None or >= nx: full x-rows."""
     Q = len(lat)
     ncells = nx * ny * nz
     S = (ncells + 127) // 128 * 128
@@ -40,11 +51,19 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
     # pert values per thread: exact for the compile-time tiles (256 x 4,
     # 256 x 2, 128 x 4 for D3Q19; 256 x 4, 256 x 2 for D3Q27), else a bound
     tiles = {(256, 4), (256, 2), (128, 4)} if Q == 19 else {(256, 4), (256, 2)}
-    if (nx, TY) in tiles and ny % TY == 0:
+    XT = TXMAX is not None
+    xs = XT and TXMAX < nx
+    compile_time = (nx, TY) in tiles and ny % TY == 0 and not XT
+    if xs:
+        IPT, HPT = -(-TXMAX * TY // NT), -(-(TXMAX + 2) * (TY + 2) // NT)
+    if compile_time:
         PPT = -(-(TY + 4) * nx // NT)
+    elif XT:
+        PPT = 2 * HPT
     else:
         PPT = (5 * HPT + 2) // 3
-    fnyb = -(-ny // TY)
+    fnxb = -(-nx // TXMAX) if xs else 1
+    fnyb = -(-ny // TY) * fnxb
     nzb = -(-nz // SZ)
     tid = np.arange(NT)
     written = np.zeros((Q, ncells), np.int32)
@@ -60,10 +79,21 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
 
     for b in range(fnyb * nzb):
         bz = b // fnyb
-        y0 = (b - bz * fnyb) * TYMAX
+        tb = b - bz * fnyb
+        yb, xb = tb // fnxb, tb % fnxb
+        y0 = yb * TYMAX
+        x0 = xb * TXMAX if xs else 0
         TY = min(TYMAX, ny - y0)      # shorter last tile (general tiles)
-        NI, HC, PR = nx * TY, nx * (TY + 2), TY + 4
-        PC = PR * nx
+        TX = min(TXMAX, nx - x0) if xs else nx
+        HW, RW = (TX + 2, TX + 4) if xs else (nx, nx)
+        NI, HC, PR = TX * TY, HW * (TY + 2), TY + 4
+        PC = PR * RW
+
+        def halo_x(hx):
+            return wrap(x0 - 1 + hx, nx) if xs else hx
+
+        def ring_x(c):
+            return wrap(x0 - 2 + c, nx) if xs else c
         assert PC <= PPT * NT and NI <= IPT * NT and HC <= HPT * NT
         z0 = bz * SZ
         z1 = min(z0 + SZ, nz)
@@ -74,8 +104,8 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
             qz = zmod(q)
             for j in range(PPT):
                 idx = np.minimum(tid + j * NT, PC - 1)
-                r = idx // nx
-                x = idx - r * nx
+                r = idx // RW
+                x = ring_x(idx - r * RW)
                 y = ((y0 + r - 2) % ny + ny) % ny
                 a = qz * nxy + y * nx + x
                 assert np.all((a >= 0) & (a < ncells)), "pert load"
@@ -87,10 +117,14 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
                 assert np.all((ri >= 0) & (ri < 5 * PC)), "ring store"
             ring[slot(q)] = (q, it)
 
-        def ring_read(q, r, x, it, phase):
+        def ring_read(q, r, x, it, phase, want_x=None):
+            """x: the ring column; want_x: the global column it must hold."""
             assert q - (z0 - 2) >= 0
-            ri = (slot(q) * PR + r) * nx + x
+            ri = (slot(q) * PR + r) * RW + x
             assert np.all((r >= 0) & (r < PR)), ("ring row", r)
+            assert np.all((x >= 0) & (x < RW)), ("ring column", x)
+            if want_x is not None:
+                assert np.all(ring_x(x) == want_x), "ring column holds another x"
             assert np.all((ri >= 0) & (ri < 5 * PC)), "ring read"
             plane, w_it = ring[slot(q)]
             assert plane == q, ("ring holds", plane, "wanted", q)
@@ -102,8 +136,8 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
             pz = zmod(p)
             for h in range(HPT):
                 idx = np.minimum(tid + h * NT, HC - 1)
-                hr = idx // nx
-                x = idx - hr * nx
+                hr = idx // HW
+                x = halo_x(idx - hr * HW)
                 y = wrap(y0 + hr - 1, ny)
                 for i in range(Q):
                     a = i * S + pz * nxy + y * nx + x
@@ -118,28 +152,60 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
         for p in range(z0 - 1, z1 + 1):
             pz = int(wrap(np.array(p), nz))
             slab = np.zeros((Q, NI), np.int32)
+            pushed = np.zeros((Q, NI), np.int32)   # pushes by computing lanes (repeats too)
+            # the last halo cell HC - 1: its halo slot and whether its wave computes
+            h2_of_last = (HC - 1) // NT
+            lane_last = (HC - 1) - h2_of_last * NT
+            computing_last = bool((compile_time and (h2_of_last + 1) * NT <= (TYMAX + 2) * nx)
+                                  or ((lane_last & ~63) + h2_of_last * NT < HC))
             store_pert(pending_pert, p)
             assert pending_pert == p + 2
             # halo phase
             for h in range(HPT):
                 idx = np.minimum(tid + h * NT, HC - 1)
-                hr = idx // nx
-                x = idx - hr * nx
-                xm, xp = np.where(x == 0, nx, x) - 1, np.where(x + 1 == nx, 0, x + 1)
+                hr = idx // HW
+                hx = idx - hr * HW
+                x = halo_x(hx)
+                c = hx + 1 if xs else x
+                cm = c - 1 if xs else np.where(c == 0, nx, c) - 1
+                cp = c + 1 if xs else np.where(c + 1 == nx, 0, c + 1)
+                xm, xp = wrap(x - 1, nx), wrap(x + 1, nx)
                 r = hr + 1
-                for (qq, rr, xx) in ((p, r, x), (p, r, xp), (p, r, xm), (p, r + 1, x),
-                                     (p, r - 1, x), (p + 1, r, x), (p - 1, r, x)):
-                    ring_read(qq, rr, xx, p, "halo")
+                for (qq, rr, cc, gx) in ((p, r, c, x), (p, r, cp, xp), (p, r, cm, xm),
+                                         (p, r + 1, c, x), (p, r - 1, c, x), (p + 1, r, c, x),
+                                         (p - 1, r, c, x)):
+                    ring_read(qq, rr, cc, p, "halo", gx)
                 real = tid + h * NT < HC  # lanes past the last halo cell repeat it
+                # the halo-wave skip: a wave collides and pushes only if its
+                # first lane is a real halo cell, or the compile-time constant
+                # FULL says every lane of this halo slot is real
+                FULL = compile_time and (h + 1) * NT <= (TYMAX + 2) * nx
+                computing = FULL | ((tid & ~63) + h * NT < HC)
+                if FULL:
+                    assert np.all(real), "FULL with a lane past the tile"
+                assert np.all(computing[real]), "a real halo cell in a skipped wave"
+                # a computing lane past the tile repeats the last halo cell, which
+                # its own (real) lane computes from the same inputs in this phase
+                rep = computing & ~real
+                if rep.any():
+                    assert computing_last, "the repeated cell is not computed"
                 for i, (cx, cy, cz) in enumerate(lat):
                     rd = hr - 1 + cy
                     ok = (rd >= 0) & (rd < TY)
-                    xd = wrap(x + cx, nx)
-                    sidx = rd * nx + xd
+                    if xs:
+                        xd = hx - 1 + cx           # tile column, kept inside the tile
+                        ok = ok & (xd >= 0) & (xd < TX)
+                        assert np.all(~ok | (x0 + xd == wrap(x + cx, nx))), "slab column"
+                    else:
+                        xd = wrap(x + cx, nx)
+                    sidx = rd * TX + xd
                     assert np.all(~ok | ((sidx >= 0) & (sidx < NI))), "slab push"
                     np.add.at(slab[i], sidx[ok & real], 1)
-            # every interior cell receives each direction from exactly one halo cell
+                    np.add.at(pushed[i], sidx[ok & computing], 1)
+            # every interior cell receives each direction from exactly one real
+            # halo cell, and every slab slot is written by a computing wave
             assert np.all(slab == 1), ("slab coverage", slab.min(), slab.max())
+            assert np.all(pushed >= 1), "slab slot written by no computing wave"
             load_pert(p + 3)
             pending_pert = p + 3
             load_plane(p + 1)
@@ -148,15 +214,20 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512):
             for k in range(IPT):
                 own = (tid + k * NT < NI) & (p > z0)
                 cell = np.minimum(tid + k * NT, NI - 1)
-                r = cell // nx
-                x = cell - r * nx
+                r = cell // TX
+                cx_ = cell - r * TX
+                x = x0 + cx_
                 y = y0 + r
-                assert np.all(y < ny)
-                xm, xp = np.where(x == 0, nx, x) - 1, np.where(x + 1 == nx, 0, x + 1)
+                assert np.all((y < ny) & (x < nx))
+                c = cx_ + 2 if xs else x
+                cm = c - 1 if xs else np.where(c == 0, nx, c) - 1
+                cp = c + 1 if xs else np.where(c + 1 == nx, 0, c + 1)
+                xm, xp = wrap(x - 1, nx), wrap(x + 1, nx)
                 rr = r + 2
-                for (qq, r2, xx) in ((z, rr, x), (z, rr, xp), (z, rr, xm), (z, rr + 1, x),
-                                     (z, rr - 1, x), (z + 1, rr, x), (z - 1, rr, x)):
-                    ring_read(qq, r2, xx, p, "interior")
+                for (qq, r2, cc, gx) in ((z, rr, c, x), (z, rr, cp, xp), (z, rr, cm, xm),
+                                         (z, rr + 1, c, x), (z, rr - 1, c, x), (z + 1, rr, c, x),
+                                         (z - 1, rr, c, x)):
+                    ring_read(qq, r2, cc, p, "interior", gx)
                 for i, (cx, cy, cz) in enumerate(lat):
                     yd, zd, xd = wrap(y + cy, ny), int(wrap(np.array(z + cz), nz)), wrap(x + cx, nx)
                     a = zd * nxy + yd * nx + xd
@@ -193,9 +264,34 @@ def test_two_step_tile_indexing_full_size_first_blocks(case):
     assert check(*case, D3Q19, full=False)
 
 
+@pytest.mark.parametrize("case", [(128, 8, 20, 4, 16), (256, 4, 130, 2, 128),
+                                  (128, 128, 128, 4, 16)])
+def test_two_step_benchmarked_512_thread_tiles(case):
+    """The compile-time 128 x 4 and 256 x 2 tiles of the benchmarked launches
+    (128^3 FP64 with 16-plane segments; 256^3 FP64 with 128-plane segments),
+    with the halo-wave skip."""
+    assert check(*case, D3Q19, full=case[0] * case[1] * case[2] < 2_000_000)
+
+
 @pytest.mark.parametrize("case", [(256, 8, 5, 4, 64), (256, 4, 9, 4, 4), (256, 12, 3, 4, 2)])
 def test_two_step_tile_indexing_1024_threads(case):
     """The 256 x 4 tile in 1024-thread blocks (one interior, two halo cells
     per thread, the second halo cell of half the threads past the tile)."""
     assert check(*case, D3Q19, NT=1024)
     assert check(256, 256, 256, 4, 64, D3Q19, full=False, NT=1024)
+
+
+# x-split general tiles of the batched launch: (nx, ny, nz, rows, planes, cols)
+XT_CASES = [(192, 20, 9, 16, 4, 32), (192, 11, 7, 5, 3, 96), (130, 9, 6, 6, 5, 44),
+            (129, 7, 5, 10, 2, 43), (256, 6, 4, 4, 4, 64), (100, 12, 3, 13, 2, 34),
+            (64, 8, 4, 8, 4, 64), (33, 5, 4, 5, 2, 33), (8, 5, 3, 2, 2, 3)]
+
+
+@pytest.mark.parametrize("lat", ["D3Q19"])
+@pytest.mark.parametrize("case", XT_CASES)
+def test_two_step_x_split_tile_indexing(case, lat):
+    """Tiles of `cols` interior columns with a halo column on each side (the
+    last tile of a row shorter), and members of an x-split batch that keep
+    full rows (cols >= nx)."""
+    nx, ny, nz, rows, planes, cols = case
+    assert check(nx, ny, nz, rows, planes, D3Q19, TXMAX=cols)
