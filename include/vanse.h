@@ -333,6 +333,36 @@ const char *vanse_last_error(vanse_t h);
  * double [Q]), in the direction order used by vanse_populations. */
 int vanse_lattice_info(int lattice, int *d, int *q, int *xi, double *w);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the sums of
+ * vanse_diagnostics computed from caller-owned arrays by the same kernels,
+ * with no handle and no allocation.
+ *   lattice    VANSE_D2Q9, VANSE_D3Q19 or VANSE_D3Q27
+ *   dims       {nx, ny, nz} as in vanse_create (nz = 1 for D2Q9); inputs of
+ *              2^31 cells or more are rejected (EINVAL)
+ *   f          device FP64 populations in natural order, SoA [Q][ncells], in
+ *              this library's direction order (the layout vanse_populations
+ *              writes)
+ *   phi        device FP64 volume fraction at the time level of f [ncells]
+ *   quad_axes  as in vanse_set_porosity
+ *   F          host double[3] constant force density, or NULL (0)
+ *   force      device FP64 per-cell force density SoA [d][ncells], or NULL
+ *   out        DEVICE FP64 [7]: out[0] = sum_x sum_i f_i, out[1..3] =
+ *              sum_x sum_i xi_i f_i, out[4..6] = sum_x F (pressure-correction
+ *              plus external forces), in the fixed order of vanse_diagnostics
+ *   stream     hipStream_t to launch on (NULL = null stream)
+ * Asynchronous: nothing is synchronised, copied to the host or allocated;
+ * the call may be captured into a graph.  The block partials go to a fixed
+ * device array of the library (7 * 1024 + 64 doubles per GPU, whatever the
+ * input size, held until the process ends) that every call on that GPU
+ * overwrites completely: calls that overlap on one GPU (other streams, or
+ * other threads) race on it and must be ordered by the caller.  Non-finite
+ * inputs give non-finite sums (no sticky state: there is no handle).
+ * Errors: EINVAL (message in vanse_last_error(NULL)), EDEVICE. */
+int vanse_diagnostics_noalloc(int lattice, const int64_t dims[3], const double *f,
+                              const double *phi, int quad_axes, const double F[3],
+                              const double *force, double *out, void *stream);
+
 /* Streaming copy of `bytes` bytes (multiple of 16) from src to dst on
  * stream: the achievable-bandwidth probe used to calibrate measurements.
  * Errors: EINVAL, EDEVICE. */

@@ -667,6 +667,53 @@ int vanse_lattice_info(int lattice, int *d, int *q, int *xi, double *w)
     return VANSE_OK;
 }
 
+int vanse_diagnostics_noalloc(int lattice, const int64_t dims[3], const double *f,
+                              const double *phi, int quad_axes, const double F[3],
+                              const double *force, double *out, void *stream)
+{
+    const char *who = "vanse_diagnostics_noalloc: ";
+    if (lattice != VANSE_D2Q9 && lattice != VANSE_D3Q19 && lattice != VANSE_D3Q27)
+        return fail(nullptr, VANSE_EINVAL, std::string(who) + "unknown lattice");
+    if (!dims) return fail(nullptr, VANSE_EINVAL, std::string(who) + "dims is NULL");
+    const int d = lattice == VANSE_D2Q9 ? 2 : 3;
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 1 || dims[a] > (1 << 30))
+            return fail(nullptr, VANSE_EINVAL, std::string(who) + "every dim must be >= 1");
+    if (d == 2 && dims[2] != 1)
+        return fail(nullptr, VANSE_EINVAL, std::string(who) + "nz must be 1 for D2Q9");
+    const int64_t ncells = dims[0] * dims[1] * dims[2];
+    if (ncells >= (int64_t(1) << 31) || dims[0] * dims[1] >= (int64_t(1) << 31))
+        return fail(nullptr, VANSE_EINVAL,
+                    std::string(who) + "nx*ny*nz must be < 2^31 (the largest input it accepts)");
+    if (!f || !phi || !out)
+        return fail(nullptr, VANSE_EINVAL, std::string(who) + "f, phi and out must not be NULL");
+    if (quad_axes != VANSE_QUAD_NONE && (quad_axes < 0 || quad_axes > 7 || (d == 2 && (quad_axes & 4))))
+        return fail(nullptr, VANSE_EINVAL, std::string(who) + "bad quad_axes mask");
+    double Fc[3] = {0.0, 0.0, 0.0};
+    if (F)
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(F[a])) return fail(nullptr, VANSE_EINVAL, std::string(who) + "F not finite");
+            if (a >= d && F[a] != 0.0)
+                return fail(nullptr, VANSE_EINVAL, std::string(who) + "z force on a 2-D lattice");
+            Fc[a] = F[a];
+        }
+    const int qmask = quad_axes == 0 ? (d == 2 ? 3 : 7) : (quad_axes == VANSE_QUAD_NONE ? 0 : quad_axes);
+    int n_axes = 0;
+    for (int b = 0; b < 3; ++b) n_axes += (qmask >> b) & 1;
+    vanse::Geometry g{};
+    g.nx = (int)dims[0];
+    g.ny = (int)dims[1];
+    g.nz = (int)dims[2];
+    g.nxy = (int)(dims[0] * dims[1]);
+    g.ncells = (int)ncells;
+    g.stride = ncells;  // the caller's arrays are dense: [Q][ncells], [d][ncells]
+    hipError_t e = vanse::launch_diagnostics_noalloc(
+        lattice, g, f, phi, n_axes ? vanse::quad_weight(n_axes) : 0.0, 2.0 * n_axes, qmask, Fc,
+        force, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "vanse_diagnostics_noalloc");
+    return VANSE_OK;
+}
+
 int vanse_copy_probe(void *dst, const void *src, int64_t bytes, void *stream)
 {
     if (!dst || !src || bytes <= 0 || bytes % 16)

@@ -187,6 +187,13 @@ hipError_t launch_moments(const Solver &s, int parity, double m, double *rho, do
                           double *u);
 hipError_t launch_populations(const Solver &s, int parity, double *f);
 hipError_t launch_diagnostics(const Solver &s, int parity, double m, double *out_dev);
+// Allocation-free diagnostics over caller-owned natural-order FP64 inputs
+// (plane stride g.stride == g.ncells); partials in a fixed per-device array.
+hipError_t launch_diagnostics_noalloc(int lattice, const Geometry &g, const double *f,
+                                      const double *phi, double wq, double n2, int qmask,
+                                      const double F[3], const double *force, double *out,
+                                      hipStream_t st);
+size_t noalloc_scratch_bytes();
 hipError_t launch_convert_pert(const Solver &s, const double *src);
 hipError_t launch_convert(const double *src, float *dst, long long n, hipStream_t st);
 // min, max and non-finite count of n FP64 values: per-block triples in

@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1398,6 +1399,80 @@ hipError_t launch_diagnostics(const Solver &s, int parity, double m, double *out
     });
     if (e != hipSuccess) return e;
     finalize_kernel<7><<<1, kReduceThreads, 0, s.stream>>>(partials, kReduceBlocks, out_dev);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reduction scratch of the allocation-free diagnostics: a fixed device array
+// (one copy per GPU, held until the process ends) for the block partials and
+// the combined sums.  Host code never passes the array's name to a kernel
+// (in host code it is a stand-in, not a device address): the device address
+// comes from hipGetSymbolAddress, taken once per device and kept below.
+constexpr int kNoAllocScratchDoubles = 7 * kReduceBlocks + 64;
+static __device__ __align__(256) double g_noalloc_scratch[kNoAllocScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of this GPU's copy of the scratch array, looked up on the
+// first call made with that device current.
+static hipError_t noalloc_scratch(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_noalloc_scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_noalloc_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_noalloc_ptr[dev];
+    return hipSuccess;
+}
+
+size_t noalloc_scratch_bytes() { return sizeof(double) * kNoAllocScratchDoubles; }
+
+// The sums of launch_diagnostics over caller-owned FP64 inputs in natural
+// order (f [Q][ncells], phi [ncells], force [d][ncells] or null): the same
+// diag_kernel and finalize_kernel, with phi = 0 + 1 * phi and plane stride
+// ncells, partials in the fixed scratch array.  Nothing is allocated.
+hipError_t launch_diagnostics_noalloc(int lattice, const Geometry &g, const double *f,
+                                      const double *phi, double wq, double n2, int qmask,
+                                      const double F[3], const double *force, double *out,
+                                      hipStream_t st)
+{
+    double *partials = nullptr;
+    hipError_t e = noalloc_scratch(&partials);
+    if (e != hipSuccess) return e;
+    StepArgs a{};
+    a.geo = g;
+    a.f = const_cast<double *>(f);
+    a.pert = phi;
+    a.eps_mean = 0.0;
+    a.m = 1.0;
+    a.omega = 1.0;
+    a.fcoef = 0.5;
+    for (int d = 0; d < 3; ++d) a.F[d] = F[d];
+    a.force = force;
+    a.wq = wq;
+    a.n2 = n2;
+    a.qmask = qmask;
+    e = dispatch(lattice, MODE_F64, [&](auto lat, auto mode) {
+        using L = decltype(lat);
+        constexpr int M = decltype(mode)::value;
+        if constexpr (M == MODE_F64)
+            diag_kernel<L, M><<<kReduceBlocks, kReduceThreads, 0, st>>>(a, 0, partials);
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    finalize_kernel<7><<<1, kReduceThreads, 0, st>>>(partials, kReduceBlocks, out);
     return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ EXPORTS = [
     "vanse_batch_create", "vanse_batch_destroy", "vanse_batch_set_stream",
     "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
     "vanse_batch_last_error", "vanse_batch_update", "vanse_batch_two_step_layout",
+    "vanse_diagnostics_noalloc",
 ]
 TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT, TUNE_NT_STORES, TUNE_TWO_STEP = 1, 2, 4, 8, 16
 
@@ -105,6 +106,7 @@ def load_library(path: str = LIB_PATH):
             "vanse_batch_last_error": (ctypes.c_char_p, [P]),
             "vanse_batch_two_step_layout": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "vanse_batch_update": (i, [P, ctypes.POINTER(P), i]),
+            "vanse_diagnostics_noalloc": (i, [i, I64P, P, P, i, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -147,6 +149,27 @@ def copy_probe(dst: torch.Tensor, src: torch.Tensor):
                               n, _stream_handle())
     if rc:
         raise VanseError(rc, lib.vanse_last_error(None).decode())
+
+
+def diagnostics_noalloc(lattice, dims, f, phi, quad_axes=0, F=None, force=None, out=None):
+    """vanse_diagnostics_noalloc: the sums of Solver.diagnostics from
+    caller-owned FP64 CUDA tensors (f [Q, ncells] natural order, phi
+    [ncells], force [d, ncells] or None) into `out` (a float64 CUDA tensor
+    of 7, allocated here when None), asynchronously on the current stream;
+    the library allocates nothing.  Returns out."""
+    lib = load_library()
+    if isinstance(lattice, str):
+        lattice = LATTICES[lattice]
+    dims = list(dims) + [1] * (3 - len(dims))
+    arr = (ctypes.c_int64 * 3)(*[int(v) for v in dims])
+    if out is None:
+        out = torch.empty(7, dtype=torch.float64, device=f.device)
+    Fh = None if F is None else (ctypes.c_double * 3)(*[float(v) for v in list(F) + [0.0] * (3 - len(F))])
+    rc = lib.vanse_diagnostics_noalloc(lattice, arr, _ptr(f), _ptr(phi), int(quad_axes), Fh,
+                                       _ptr(force), _ptr(out), _stream_handle())
+    if rc:
+        raise VanseError(rc, lib.vanse_last_error(None).decode())
+    return out
 
 
 class Solver:
