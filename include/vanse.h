@@ -212,7 +212,10 @@ int vanse_batch_set_stream(vanse_batch_t b, void *stream);
  *       is split into equal segments of at most 32 planes (at most 24, 16,
  *       12 or 8 when a host-side estimate of the launch finds the batch too
  *       small to fill the GPU with 32; vanse_batch_two_step_layout reports
- *       the result).  Every member gets a second population array
+ *       the result).  On D3Q19, when a member's full rows do not fit a
+ *       block (nx > 340; FP64 nx > 170), general tiles split the x-rows of
+ *       wide members into segments of at least 48 columns with a halo
+ *       column on each side (vanse_batch_two_step_tiles reports them).  Every member gets a second population array
  *       (allocated here, kept by the member's solver: its population memory
  *       doubles).  Used for every group of 4 steps of a chunk while all
  *       members sit at even time levels (two launches, so each member ends
@@ -253,6 +256,11 @@ int vanse_batch_autotune(vanse_batch_t b, int steps_per_trial, int *block, int *
  * two-step layout is in effect (the flag is not set, the lattice is 2-D, or a
  * member has no tile).  Host only: no GPU work. */
 int vanse_batch_two_step_layout(vanse_batch_t b, int count, int *rows, int *planes);
+
+/* As vanse_batch_two_step_layout, and cols[k]: the interior columns of member
+ * k's tile (nx for tiles of full x-rows; fewer when the batch splits x-rows,
+ * see vanse_batch_set_tuning).  Host only.  Errors: EINVAL, ESTATE. */
+int vanse_batch_two_step_tiles(vanse_batch_t b, int count, int *cols, int *rows, int *planes);
 
 /* Last error message of b (NULL: of the last failed vanse_batch_create). */
 const char *vanse_batch_last_error(vanse_batch_t b);

@@ -50,6 +50,7 @@ struct vanse_batch {
     bool two_step = false;              // requested
     bool fused_ok = false;              // every member has a general tile
     int uni_nx = 0, uni_rows = 0;       // the members' common compile-time tile (0: general tiles)
+    bool xt = false;                    // general tiles with x-split members
     unsigned nblocks2 = 0;
     size_t lds2 = 0;                    // LDS bytes per block of the two-step grid
     vanse::BatchMember *d_members2 = nullptr;
@@ -57,6 +58,7 @@ struct vanse_batch {
     size_t d_members2_cap = 0, cap_owner2 = 0;
     std::vector<void *> layout_f2;      // members' second arrays in the two-step table
     std::vector<int> rows2, planes2;    // members' tile rows and z-planes per segment
+    std::vector<int> cols2;             // members' tile columns (nx: full rows)
     hipGraphExec_t gexec2 = nullptr;    // a full chunk of two-step launches
 };
 
@@ -108,6 +110,9 @@ StepArgs step_args(const Solver &s, int64_t n)
     a.fsz = (unsigned)std::max(s.fused_planes, 1);
     a.fnyb = (unsigned)((s.geo.ny + (int)a.fty - 1) / (int)a.fty);
     a.fd_fnyb = make_fastdiv(std::max(a.fnyb, 1u));
+    a.ftx = (unsigned)s.geo.nx;  // full rows
+    a.fnxb = 1;
+    a.fd_fnxb = make_fastdiv(1u);
     a.trash = s.scratch ? s.scratch + kTrashSlot : nullptr;
     return a;
 }
@@ -804,15 +809,19 @@ int balanced_planes(int nz, int target)
 // of the general tile per CU); a block costs its tile's cells per plane times
 // its planes plus 3, the planes a segment reads and collides beyond its own.
 double gen_launch_estimate(const std::vector<const vanse::Solver *> &ms,
-                           const std::vector<int> &rows, int target, int cus)
+                           const std::vector<int> &rows, const std::vector<int> &cols,
+                           int target, int cus)
 {
     std::vector<double> cost;
     for (size_t k = 0; k < ms.size(); ++k) {
         const vanse::Geometry &g = ms[k]->geo;
         const int r = rows[k], P = balanced_planes(g.nz, target), fnyb = (g.ny + r - 1) / r;
+        const int c = std::min(cols[k], g.nx), fnxb = (g.nx + c - 1) / c;
         for (int z0 = 0; z0 < g.nz; z0 += P)
             for (int yb = 0; yb < fnyb; ++yb)
-                cost.push_back(double(std::min(P, g.nz - z0) + 3) * std::min(r, g.ny - yb * r) * g.nx);
+                for (int xb = 0; xb < fnxb; ++xb)
+                    cost.push_back(double(std::min(P, g.nz - z0) + 3) * std::min(r, g.ny - yb * r) *
+                                   std::min(c, g.nx - xb * c));
     }
     const size_t n = cost.size(), q = n / 8, rem = n % 8;
     const int per_xcd = std::max(1, cus / 8);
@@ -846,17 +855,17 @@ double gen_launch_estimate(const std::vector<const vanse::Solver *> &ms,
 // fastest target or one within 3% of it.  The estimate counts one block per
 // CU also where two fit: with two, it picked segments too short.
 int segment_target(const std::vector<const vanse::Solver *> &ms, const std::vector<int> &rows,
-                   int base, std::initializer_list<int> shorter)
+                   const std::vector<int> &cols, int base, std::initializer_list<int> shorter)
 {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 8)
         cus = 256;
-    const double base_t = gen_launch_estimate(ms, rows, base, cus);
+    const double base_t = gen_launch_estimate(ms, rows, cols, base, cus);
     int best = base;
     double best_t = base_t;
     for (int target : shorter) {
-        const double t = gen_launch_estimate(ms, rows, target, cus);
+        const double t = gen_launch_estimate(ms, rows, cols, target, cus);
         if (t < best_t) {
             best_t = t;
             best = target;
@@ -894,22 +903,47 @@ int batch_layout2(vanse_batch *b)
         uni_rows = r;
     }
     if (uni_rows == 0) uni_nx = 0;
-    auto tile_rows = [&](const Solver &s) {
-        return uni_rows ? uni_rows : vanse::batch_fused_rows(s);
+    // General tiles: full x-rows; on D3Q19, x-split tiles when a member's
+    // full rows do not fit a block (FP64 wider than 170 cells, FP32/FP16
+    // wider than 340), so that such batches still take the two-step launch.
+    // Where full rows fit they are kept even if a split loads fewer halo
+    // cells: measured on 192^3 and 250^3 solves and the served stream,
+    // full-row tiles of 2-3 rows beat every split of 32-125 columns (FP32
+    // 192^3: 46.7 GLUPS against 33-40), although the splits load fewer halo
+    // cells.
+    std::vector<int> xt_cols(b->count, 0), xt_rows(b->count, 0);
+    bool xt = false;
+    if (uni_rows == 0 && b->lattice == VANSE_D3Q19) {
+        bool ok_xt = true, split = false;
+        for (int k = 0; k < b->count && ok_xt; ++k) {
+            const Solver &s = b->members[k]->s;
+            if (!vanse::batch_xt_tile(s, &xt_cols[k], &xt_rows[k])) ok_xt = false;
+            else split = split || xt_cols[k] < s.geo.nx;
+        }
+        xt = ok_xt && split;
+    }
+    auto tile_rows = [&](int k) {
+        const Solver &s = b->members[k]->s;
+        return uni_rows ? uni_rows : (xt ? xt_rows[k] : vanse::batch_fused_rows(s));
+    };
+    auto tile_cols = [&](int k) {
+        const Solver &s = b->members[k]->s;
+        return xt ? std::min(xt_cols[k], s.geo.nx) : s.geo.nx;
     };
     int target = 0;
     {
         std::vector<const Solver *> ms;
-        std::vector<int> rows;
+        std::vector<int> rows, cols;
         for (int k = 0; k < b->count; ++k) {
             const Solver &s = b->members[k]->s;
-            const int r = tile_rows(s);
+            const int r = tile_rows(k);
             if (r == 0) return VANSE_OK;  // no tile: single steps only
             ms.push_back(&s);
             rows.push_back(r);
+            cols.push_back(tile_cols(k));
         }
-        target = uni_rows ? segment_target(ms, rows, 64, {32, 16, 8})
-                          : segment_target(ms, rows, 32, {24, 16, 12, 8});
+        target = uni_rows ? segment_target(ms, rows, cols, 64, {32, 16, 8})
+                          : segment_target(ms, rows, cols, 32, {24, 16, 12, 8});
     }
     auto tile_planes = [&](const Solver &s) { return balanced_planes(s.geo.nz, target); };
     std::vector<vanse::BatchMember> mem(b->count);
@@ -918,11 +952,13 @@ int batch_layout2(vanse_batch *b)
     size_t lds = 0;
     for (int k = 0; k < b->count; ++k) {
         const Solver &s = b->members[k]->s;
-        const int rows = tile_rows(s);
+        const int rows = tile_rows(k), cols = tile_cols(k);
         if (rows == 0) return VANSE_OK;
         const int planes = tile_planes(s);
-        lds = std::max(lds, vanse::fused_lds_bytes(s.q, s.mode, s.geo.nx, rows));
-        const unsigned fnyb = (unsigned)((s.geo.ny + rows - 1) / rows);
+        lds = std::max(lds, cols < s.geo.nx ? vanse::fused_lds_bytes_xt(s.q, s.mode, cols, rows)
+                                            : vanse::fused_lds_bytes(s.q, s.mode, s.geo.nx, rows));
+        const unsigned fnxb = (unsigned)((s.geo.nx + cols - 1) / cols);
+        const unsigned fnyb = (unsigned)((s.geo.ny + rows - 1) / rows) * fnxb;
         const unsigned nzb = (unsigned)((s.geo.nz + planes - 1) / planes);
         if ((size_t)begin + (size_t)fnyb * nzb > 0x7fffffffu) return VANSE_OK;
         mem[k].block_begin = begin;
@@ -931,6 +967,7 @@ int batch_layout2(vanse_batch *b)
     }
     if (lds > (size_t)vanse::kFusedMaxLds) return VANSE_OK;
     b->layout_f2.assign(b->count, nullptr);
+    b->cols2.assign(b->count, 0);
     for (int k = 0; k < b->count; ++k) {
         Solver &s = b->members[k]->s;
         if (!s.f_alt) {
@@ -942,16 +979,20 @@ int batch_layout2(vanse_batch *b)
                                                   hipGetErrorString(e));
             }
         }
-        const int rows = tile_rows(s);
+        const int rows = tile_rows(k), cols = tile_cols(k);
         vanse::StepArgs a = vanse::step_args(s, s.t);
         a.fty = (unsigned)rows;
         a.fsz = (unsigned)tile_planes(s);
-        a.fnyb = (unsigned)((s.geo.ny + rows - 1) / rows);
+        a.ftx = (unsigned)cols;
+        a.fnxb = (unsigned)((s.geo.nx + cols - 1) / cols);
+        a.fd_fnxb = vanse::make_fastdiv(a.fnxb);
+        a.fnyb = (unsigned)((s.geo.ny + rows - 1) / rows) * a.fnxb;
         a.fd_fnyb = vanse::make_fastdiv(a.fnyb);
         a.f2 = s.f_alt;
         mem[k].a = a;
         owner.insert(owner.end(), mem[k].nblocks, (unsigned)k);
         b->layout_f2[k] = s.f_alt;
+        b->cols2[k] = cols;
     }
     hipError_t e;
     if (!b->d_members2 || (size_t)b->count > b->d_members2_cap) {
@@ -984,6 +1025,7 @@ int batch_layout2(vanse_batch *b)
     b->lds2 = lds;
     b->uni_nx = uni_nx;
     b->uni_rows = uni_rows;
+    b->xt = xt;
     b->fused_ok = true;
     return VANSE_OK;
 }
@@ -1075,9 +1117,9 @@ hipError_t batch_launch(vanse_batch *b, int j, hipStream_t st)
 hipError_t batch_launch2(vanse_batch *b, int j, int swap, hipStream_t st)
 {
     const double *mtab = reinterpret_cast<const double *>(b->d_tab);
-    return vanse::launch_batch_fused(b->lattice, b->mode, b->uni_nx, b->uni_rows, b->nblocks2,
-                                     b->lds2, b->d_members2, b->d_owner2, mtab, j, b->count, swap,
-                                     st);
+    return vanse::launch_batch_fused(b->lattice, b->mode, b->uni_nx, b->uni_rows, b->xt,
+                                     b->nblocks2, b->lds2, b->d_members2, b->d_owner2, mtab, j,
+                                     b->count, swap, st);
 }
 
 // Steps 0 .. k-1 of a chunk: with `two`, each group of 4 steps is two
@@ -1401,6 +1443,21 @@ int vanse_batch_two_step_layout(vanse_batch_t b, int count, int *rows, int *plan
     if (!b->two_step || !b->fused_ok)
         return bfail(b, VANSE_ESTATE, "vanse_batch_two_step_layout: no two-step layout in effect");
     for (int k = 0; k < count; ++k) {
+        rows[k] = b->rows2[k];
+        planes[k] = b->planes2[k];
+    }
+    return VANSE_OK;
+}
+
+int vanse_batch_two_step_tiles(vanse_batch_t b, int count, int *cols, int *rows, int *planes)
+{
+    if (!b) return bfail(nullptr, VANSE_EINVAL, "vanse_batch_two_step_tiles: NULL batch");
+    if (count != b->count || !cols || !rows || !planes)
+        return bfail(b, VANSE_EINVAL, "vanse_batch_two_step_tiles: count differs from the members or NULL array");
+    if (!b->two_step || !b->fused_ok)
+        return bfail(b, VANSE_ESTATE, "vanse_batch_two_step_tiles: no two-step layout in effect");
+    for (int k = 0; k < count; ++k) {
+        cols[k] = b->cols2.size() == (size_t)count ? b->cols2[k] : b->members[k]->s.geo.nx;
         rows[k] = b->rows2[k];
         planes[k] = b->planes2[k];
     }

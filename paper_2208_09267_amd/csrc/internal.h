@@ -65,8 +65,11 @@ struct StepArgs {
     double m2;           // modulation m(n + 1) of the second step
     unsigned fty;        // full x-rows per tile
     unsigned fsz;        // z-planes per tile segment
-    unsigned fnyb;       // tiles per z-segment (ny / fty)
+    unsigned fnyb;       // tiles per z-segment (ny / fty; x-split tiles: times fnxb)
     FastDiv fd_fnyb;
+    unsigned ftx;        // x-split general tiles: interior columns per tile (>= nx: full rows)
+    unsigned fnxb;       //   and tiles per x-row
+    FastDiv fd_fnxb;
     void *trash;         // 8-byte device slot for discarded stores
 };
 
@@ -174,15 +177,25 @@ hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, u
                              hipStream_t st);
 // Rows of a solve's general tile in the batched two-step launch (0: none).
 int batch_fused_rows(const Solver &s);
+// The general tile of a D3Q19 solve in a batched two-step launch with x-split
+// members: full rows (*cols = nx) where they fit a block, else *cols >= 48
+// interior columns of a split of the x-rows and *rows rows, chosen to load
+// the fewest halo cells per interior cell; false if the solve has neither.
+bool batch_xt_tile(const Solver &s, int *cols, int *rows);
+// LDS of one block of an x-split tile (cols < nx): slab and a ring of 5
+// perturbation planes of (rows + 4) x (cols + 4) values.
+size_t fused_lds_bytes_xt(int q, int mode, int cols, int rows);
 // Rows of the compile-time tile (nx a compile-time constant) that a batched
 // two-step launch uses when every member has this nx and a multiple of the
 // rows in y (0: none for this lattice, mode and size).
 int batch_uniform_rows(int lattice, int mode, int nx, int ny);
 // uni_nx, uni_rows: the members' common compile-time tile, or 0, 0 for
 // general tiles (each member's own rows).
-hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, unsigned nblocks,
-                              size_t lds, const BatchMember *members, const unsigned *owner,
-                              const double *mtab, int j, int count, int swap, hipStream_t st);
+// xt: general tiles with x-split members (batch_xt_tile), D3Q19 only.
+hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, bool xt,
+                              unsigned nblocks, size_t lds, const BatchMember *members,
+                              const unsigned *owner, const double *mtab, int j, int count,
+                              int swap, hipStream_t st);
 hipError_t launch_moments(const Solver &s, int parity, double m, double *rho, double *p,
                           double *u);
 hipError_t launch_populations(const Solver &s, int parity, double *f);

@@ -108,6 +108,16 @@ __device__ __forceinline__ unsigned fdiv(unsigned n, const FastDiv &f)
     return (unsigned)(((unsigned long long)n * f.m) >> f.s);
 }
 
+// The multiplier of make_fastdiv computed on the device (divisors < 2^31).
+__device__ __forceinline__ FastDiv make_fastdiv_dev(unsigned d)
+{
+    FastDiv f;
+    const unsigned l = d > 1 ? 32u - (unsigned)__clz((int)(d - 1)) : 0u;  // ceil(log2 d)
+    f.s = 31 + l;
+    f.m = (unsigned)(((1ull << f.s) + d - 1) / d);
+    return f;
+}
+
 // Global memory access at a 32-bit byte offset from a base pointer.  With a
 // wave-uniform base the compiler emits the scalar-base (saddr) form, so a
 // lane carries one 32-bit offset instead of a 64-bit address.  The access
@@ -509,10 +519,18 @@ __global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__re
 // per lane, accesses use 32-bit element offsets, which the host allows only
 // when every array's byte size fits 32 bits) and a shorter last tile when fty
 // does not divide ny; otherwise nx is a multiple of 64 and fty divides ny.
-template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT>
+// XT (general tiles only): the tiles of a z-segment also split the x-rows
+// into segments of a.ftx columns (a shorter last one), numbered x-fastest;
+// such a tile adds a halo column on each side (its x-neighbours recompute
+// them, as its outer rows), and its phi ring spans the tile's columns plus
+// two on each side.  A member whose a.ftx covers its whole row (a.ftx >= nx)
+// keeps the full-row indexing of the general tile (no halo columns: x wraps
+// inside the row).  Needs nx >= 8 when a.ftx < nx.
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT, bool XT = false>
 __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
 {
     static_assert(L::D == 3, "two-step launch: 3-D lattices only");
+    static_assert(!XT || GEN, "x-split tiles are general tiles");
     using St = Storage<MODE>;
     using T = typename St::T;
     using R = typename St::R;
@@ -523,18 +541,34 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
     constexpr int RING = 5;                 // pert planes p-2 .. p+2
     // pert values per thread and plane: exact for the compile-time tiles,
     // else a bound from the halo cells per thread ((rows + 4) / (rows + 2) <= 5/3)
-    constexpr int PPT = (NXC > 0 && TYC > 0) ? ((TYC + 4) * NXC + NT - 1) / NT : (5 * HPT + 2) / 3;
+    // (x-split tiles: (rows + 4)(cols + 4) <= 2 (rows + 2)(cols + 2) whenever
+    // rows * cols >= 8, which the host ensures)
+    constexpr int PPT = (NXC > 0 && TYC > 0) ? ((TYC + 4) * NXC + NT - 1) / NT
+                                             : (XT ? 2 * HPT : (5 * HPT + 2) / 3);
     extern __shared__ __align__(16) unsigned char fused_lds[];
 
     const int nx = NXC ? NXC : a.geo.nx, ny = a.geo.ny, nz = a.geo.nz, nxy = a.geo.nxy;
     const long long S = a.geo.stride;
     const unsigned bz = fdiv(b, a.fd_fnyb);
-    const int y0 = (int)(b - bz * a.fnyb) * (TYC ? TYC : (int)a.fty);
+    const unsigned tb = b - bz * a.fnyb;  // tile within its z-segment
+    unsigned yb = tb;
+    int x0 = 0;                           // first interior column (x-split tiles)
+    if constexpr (XT) {
+        yb = fdiv(tb, a.fd_fnxb);
+        x0 = (int)(tb - yb * a.fnxb) * (int)a.ftx;
+    }
+    const int y0 = (int)yb * (TYC ? TYC : (int)a.fty);
     const int TY = TYC ? TYC : (GEN ? min((int)a.fty, ny - y0) : (int)a.fty);
-    const int NI = nx * TY;          // interior cells of one plane of the tile
-    const int HC = NI + 2 * nx;      // cells of one plane with the two outer rows
+    // x-split: interior columns TX, halo row width HW = TX + 2, ring row width
+    // RW = TX + 4; otherwise all three are nx (full rows, x wraps in the row)
+    const bool xs = XT && (int)a.ftx < nx;
+    const int TX = xs ? min((int)a.ftx, nx - x0) : nx;
+    const int HW = xs ? TX + 2 : nx;
+    const int RW = xs ? TX + 4 : nx;
+    const int NI = TX * TY;          // interior cells of one plane of the tile
+    const int HC = HW * (TY + 2);    // cells of one plane with the two outer rows
     const int PR = TY + 4;           // pert rows per plane: y0-2 .. y0+TY+1
-    const int PC = PR * nx;
+    const int PC = PR * RW;
     T *__restrict__ slab = reinterpret_cast<T *>(fused_lds);
     R *__restrict__ ring =
         reinterpret_cast<R *>(fused_lds + ((size_t)Q * NI * sizeof(T) + 15) / 16 * 16);
@@ -558,27 +592,46 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         if constexpr (GEN) return (int)r;
         else return (int)__builtin_amdgcn_readfirstlane(r);
     };
+    // rows of halo, ring and interior cell indices: row widths HW, RW, TX
+    // (x-split tiles: divisors of this tile, found once; otherwise nx)
+    FastDiv fd_hw = a.fd_nx, fd_rw = a.fd_nx, fd_tx = a.fd_nx;
+    if constexpr (XT) {
+        if (xs) {
+            fd_hw = make_fastdiv_dev((unsigned)HW);
+            fd_rw = make_fastdiv_dev((unsigned)RW);
+            fd_tx = make_fastdiv_dev((unsigned)TX);
+        }
+    }
+    auto hrow = [&](int idx) { if constexpr (XT) return (int)fdiv((unsigned)idx, fd_hw); else return row_of(idx); };
+    auto rrow = [&](int idx) { if constexpr (XT) return (int)fdiv((unsigned)idx, fd_rw); else return row_of(idx); };
+    auto irow = [&](int idx) { if constexpr (XT) return (int)fdiv((unsigned)idx, fd_tx); else return row_of(idx); };
+    // global column of halo column hx (x-split: x0 - 1 + hx, wrapped) and of
+    // ring column c (x0 - 2 + c, wrapped); full rows: the column itself
+    auto halo_x = [&](int hx) { return xs ? wrap(x0 - 1 + hx, nx) : hx; };
+    auto ring_x = [&](int c) { return xs ? wrap(x0 - 2 + c, nx) : c; };
     // element offset -> byte offset (GEN: 32-bit, checked on the host)
     auto boff = [](int elem, unsigned size) { return (unsigned)elem * size; };
     // Ring slot s holds the pert rows of one plane at ring + s * PC; plane q
     // lives in slot (q - z0 + 2) mod 5.  The loop keeps the slots of planes
     // p-2 .. p+2 in wave-uniform registers and rotates them per plane.
     // phi stencil, external + per-cell force and collision of one cell at
-    // (x, y, z) (y, z wave-uniform; r = y - y0 + 2 its ring row; rm, r0, rp
-    // the ring planes of z - 1, z, z + 1) on the decoded values v, at
-    // modulation mm
-    auto update = [&](R (&v)[Q], int x, int y, int r, const R *rm, const R *r0, const R *rp,
-                      int z, R mm) {
-        const int xm = (x == 0 ? nx : x) - 1, xp = (x + 1 == nx) ? 0 : x + 1;
-        const R *row = r0 + r * nx;
+    // (x, y, z) (y, z wave-uniform unless GEN; r its ring row, c its ring
+    // column: x itself for full rows, where the x-neighbours wrap in the row;
+    // rm, r0, rp the ring planes of z - 1, z, z + 1) on the decoded values v,
+    // at modulation mm
+    auto update = [&](R (&v)[Q], int x, int y, int r, int c, const R *rm, const R *r0,
+                      const R *rp, int z, R mm) {
+        const int cm = xs ? c - 1 : (c == 0 ? nx : c) - 1;
+        const int cp = xs ? c + 1 : ((c + 1 == nx) ? 0 : c + 1);
+        const R *row = r0 + r * RW;
         R e[7];
-        e[0] = phi_of(em, mm, row[x]);
-        e[1] = phi_of(em, mm, row[xp]);
-        e[2] = phi_of(em, mm, row[xm]);
-        e[3] = phi_of(em, mm, row[nx + x]);
-        e[4] = phi_of(em, mm, row[x - nx]);
-        e[5] = phi_of(em, mm, rp[r * nx + x]);
-        e[6] = phi_of(em, mm, rm[r * nx + x]);
+        e[0] = phi_of(em, mm, row[c]);
+        e[1] = phi_of(em, mm, row[cp]);
+        e[2] = phi_of(em, mm, row[cm]);
+        e[3] = phi_of(em, mm, row[RW + c]);
+        e[4] = phi_of(em, mm, row[c - RW]);
+        e[5] = phi_of(em, mm, rp[r * RW + c]);
+        e[6] = phi_of(em, mm, rm[r * RW + c]);
         R I, gx, gy, gz;
         eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
         R Fex = R(a.F[0]), Fey = R(a.F[1]), Fez = R(a.F[2]);
@@ -603,8 +656,8 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
     auto load_cell = [&](T (&raw_h)[Q], int h, int p) {
         const int pz = zmod(p);
         const int idx = min(tid + h * NT, HC - 1);
-        const int hr = row_of(idx);
-        const int x = idx - hr * nx;
+        const int hr = hrow(idx);
+        const int x = halo_x(idx - hr * HW);
         const int y = wrap(y0 + hr - 1, ny);
         if constexpr (GEN) {
             const unsigned o = boff(pz * nxy + y * nx + x, sizeof(T));
@@ -626,8 +679,8 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         static_for<0, PPT>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             const int idx = min(tid + j * NT, PC - 1);
-            const int r = row_of(idx);
-            const int x = idx - r * nx;
+            const int r = rrow(idx);
+            const int x = ring_x(idx - r * RW);
             const int y = ((y0 + r - 2) % ny + ny) % ny;
             if constexpr (GEN)
                 ph[j] = ld<R, false>(pert, boff(qz * nxy + y * nx + x, sizeof(R)));
@@ -674,8 +727,9 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         static_for<0, HPT>([&](auto hc) {
             constexpr int h = decltype(hc)::value;
             const int idx = min(tid + h * NT, HC - 1);
-            const int hr = row_of(idx);
-            const int x = idx - hr * nx;
+            const int hr = hrow(idx);
+            const int hx = idx - hr * HW;   // halo column (full rows: x)
+            const int x = halo_x(hx);
             R v[Q];
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
@@ -690,14 +744,20 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
             // collision and the pushes
             constexpr bool FULL = !GEN && NXC > 0 && TYC > 0 && (h + 1) * NT <= (TYC + 2) * NXC;
             if (FULL || (tid & ~63) + h * NT < HC) {
-                update(v, x, wrap(y0 + hr - 1, ny), hr + 1, ring_m1, ring_0, ring_p1, pz, R(a.m));
-                // destination rows hr - 1 + cy of the slab and wrapped columns x + cx
-                const int Ro[3] = {(hr - 2) * nx, (hr - 1) * nx, hr * nx};
-                const int Xd[3] = {(x == 0 ? nx : x) - 1, x, (x + 1 == nx) ? 0 : x + 1};
+                update(v, x, wrap(y0 + hr - 1, ny), hr + 1, xs ? hx + 1 : x, ring_m1, ring_0,
+                       ring_p1, pz, R(a.m));
+                // destination rows hr - 1 + cy of the slab and columns x + cx
+                // (full rows: wrapped in the row; x-split: hx - 1 + cx, kept
+                // inside the tile)
+                const int Ro[3] = {(hr - 2) * TX, (hr - 1) * TX, hr * TX};
+                const int Xd[3] = {xs ? hx - 2 : (x == 0 ? nx : x) - 1, xs ? hx - 1 : x,
+                                   xs ? hx : ((x + 1 == nx) ? 0 : x + 1)};
                 static_for<0, Q>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     const int r = hr - 1 + L::cy[i];
-                    if ((unsigned)r < (unsigned)TY)  // wave-uniform unless GEN
+                    bool in = (unsigned)r < (unsigned)TY;  // wave-uniform unless GEN
+                    if constexpr (XT) in = in && (unsigned)Xd[L::cx[i] + 1] < (unsigned)TX;
+                    if (in)
                         slab[i * NI + Ro[L::cy[i] + 1] + Xd[L::cx[i] + 1]] = St::encode(v[i]);
                 });
             }
@@ -717,8 +777,9 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
                 constexpr int i = decltype(ic)::value;
                 t[i] = St::decode(slab[i * NI + cell]);
             });
-            const int r = row_of(cell);
-            const int x = cell - r * nx;
+            const int r = irow(cell);
+            const int cx = cell - r * TX;   // interior column (full rows: x)
+            const int x = x0 + cx;
             const int y = y0 + r;
             R w[Q];
             static_for<0, Q>([&](auto ic) {
@@ -727,7 +788,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
                 else if constexpr (L::cz[i] == 0) w[i] = mid[k][i];
                 else w[i] = t[i];
             });
-            update(w, x, y, r + 2, ring_m2, ring_m1, ring_0, z, R(a.m2));
+            update(w, x, y, r + 2, xs ? cx + 2 : x, ring_m2, ring_m1, ring_0, z, R(a.m2));
             // push to x + xi_i: wrapped rows (wave-uniform) and columns of a.f2
             const int Yo[3] = {((y == 0 ? ny : y) - 1) * nx, y * nx,
                                ((y + 1 == ny) ? 0 : y + 1) * nx};
@@ -804,7 +865,7 @@ __global__ void __launch_bounds__(NT, (fused_waves_per_simd<L, MODE, IPT, HPT, N
 // its second array (odd launch of a chunk).  GEN: general tiles, each member
 // with its own rows; otherwise every member has the compile-time tile NXC x
 // TYC of the single-solve launch.
-template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT>
+template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT, bool XT>
 __global__ void __launch_bounds__(NT, (fused_waves_per_simd<L, MODE, IPT, HPT, NXC, GEN, NT>()))
     batch_fused2_kernel(const BatchMember *__restrict__ members, const unsigned *__restrict__ owner,
                         const double *__restrict__ mtab, int j, int count, int swap)
@@ -819,7 +880,7 @@ __global__ void __launch_bounds__(NT, (fused_waves_per_simd<L, MODE, IPT, HPT, N
         a.f = a.f2;
         a.f2 = t;
     }
-    fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN, NT>(a, b - members[s].block_begin);
+    fused2_tile<L, MODE, IPT, HPT, NXC, TYC, GEN, NT, XT>(a, b - members[s].block_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1258,16 +1319,66 @@ int batch_uniform_rows(int lattice, int mode, int nx, int ny)
     return (rows > 0 && ny % rows == 0) ? rows : 0;
 }
 
-hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, unsigned nblocks,
-                              size_t lds, const BatchMember *members, const unsigned *owner,
-                              const double *mtab, int j, int count, int swap, hipStream_t st)
+size_t fused_lds_bytes_xt(int q, int mode, int cols, int rows)
+{
+    const size_t elem = mode == MODE_F64 ? 8 : (mode == MODE_F32S ? 4 : 2);
+    const size_t slab = ((size_t)q * cols * rows * elem + 15) / 16 * 16;
+    const size_t ring = (size_t)5 * (rows + 4) * (cols + 4) * (mode == MODE_F64 ? 8 : 4);
+    return slab + ring;
+}
+
+// Full rows where they fit a block (measured faster than any split on FP32
+// 192^3 and 250^3 solves: 46.7 and 48.3 GLUPS against 33-45); otherwise the
+// split of the x-rows into k >= 2 segments of at least 48 columns with the
+// most interior cells per loaded halo-plane cell (on FP64 192^3 and 250^3,
+// 48-50 columns gave 22.1-24.2 GLUPS, 32 columns 20.6-22.3, 64 or more
+// 19.0-21.4).
+bool batch_xt_tile(const Solver &s, int *cols, int *rows)
+{
+    if (s.lattice != 1 || s.d != 3 || (long long)s.geo.ncells * 8 >= (1ll << 32)) return false;
+    const int nx = s.geo.nx, ny = s.geo.ny;
+    const int full = batch_fused_rows(s);
+    if (full > 0) {
+        *cols = nx;
+        *rows = full;
+        return true;
+    }
+    // a 512-thread block: one interior cell per thread, two halo cells (FP64:
+    // one), as the general full-row tile
+    const int ni_max = kFusedThreads, hc_max = s.mode == MODE_F64 ? kFusedThreads : 2 * kFusedThreads;
+    int best_c = 0, best_r = 0;
+    double best = 0.0;  // interior cells per loaded cell
+    for (int k = 2; k <= 16; ++k) {
+        const int c = (nx + k - 1) / k;
+        if (c < 48) break;
+        const int r = std::min(std::min(ni_max / c, hc_max / (c + 2) - 2), ny);
+        if (r < 1) continue;
+        if (fused_lds_bytes_xt(s.q, s.mode, c, r) > (size_t)kFusedMaxLds) continue;
+        const double eff = (double)c * r / ((double)(c + 2) * (r + 2));
+        if (eff > best) {
+            best = eff;
+            best_c = c;
+            best_r = r;
+        }
+    }
+    if (best_r == 0) return false;
+    *cols = best_c;
+    *rows = best_r;
+    return true;
+}
+
+hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, bool xt,
+                              unsigned nblocks, size_t lds, const BatchMember *members,
+                              const unsigned *owner, const double *mtab, int j, int count,
+                              int swap, hipStream_t st)
 {
     if (lattice == 0 || lds > (size_t)kFusedMaxLds) return hipErrorInvalidValue;
     hipError_t rc = hipErrorInvalidValue;
     bool launched = false;
     // one instantiation: IPT, HPT (of a 512-thread block), compile-time nx /
     // rows (0, 0: general tiles), threads per block
-    auto go = [&](auto lat, auto m, auto ic, auto hc, auto nxc, auto tyc, auto ntc) {
+    auto go = [&](auto lat, auto m, auto ic, auto hc, auto nxc, auto tyc, auto ntc,
+                  auto xtc) {
         using L = decltype(lat);
         constexpr int M = decltype(m)::value;
         constexpr int I = decltype(ic)::value;
@@ -1275,6 +1386,7 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, u
         constexpr int NXC = decltype(nxc)::value;
         constexpr int TYC = decltype(tyc)::value;
         constexpr int NTC = decltype(ntc)::value;
+        constexpr bool XT = decltype(xtc)::value;
         constexpr int KI = (I * kFusedThreads + NTC - 1) / NTC;
         constexpr int KH = (H * kFusedThreads + NTC - 1) / NTC;
         constexpr bool GEN = NXC == 0;
@@ -1282,8 +1394,8 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, u
         constexpr bool compiled =
             GEN ? fused_compiled_gen(LAT, M, I, H) : fused_compiled(LAT, M, I, H, NXC);
         if constexpr (compiled) {
-            if (launched || NXC != uni_nx || TYC != uni_rows) return;
-            auto *fn = &batch_fused2_kernel<L, M, KI, KH, NXC, TYC, GEN, NTC>;
+            if (launched || NXC != uni_nx || TYC != uni_rows || XT != xt) return;
+            auto *fn = &batch_fused2_kernel<L, M, KI, KH, NXC, TYC, GEN, NTC, XT>;
             static std::atomic<unsigned long long> raised{0};
             int dev = 0;
             if ((rc = hipGetDevice(&dev)) != hipSuccess) return;
@@ -1314,15 +1426,20 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, u
             // one); the compile-time tiles of batch_uniform_rows
             using N512 = std::integral_constant<int, kFusedThreads>;
             using N1024 = std::integral_constant<int, 2 * kFusedThreads>;
-            if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{}, N512{});
-            else go(lat, m, C1{}, C2{}, C0{}, C0{}, N512{});
+            using F = std::false_type;
+            using X = std::true_type;
+            if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{}, N512{}, F{});
+            else go(lat, m, C1{}, C2{}, C0{}, C0{}, N512{}, F{});
             if constexpr (std::is_same<L, D3Q19>::value) {
-                go(lat, m, C2{}, C3{}, C256{}, C4{}, N1024{});
-                go(lat, m, C1{}, C2{}, C256{}, C2{}, N512{});
-                go(lat, m, C1{}, C2{}, C128{}, C4{}, N512{});
+                // general tiles with x-split members
+                if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{}, N512{}, X{});
+                else go(lat, m, C1{}, C2{}, C0{}, C0{}, N512{}, X{});
+                go(lat, m, C2{}, C3{}, C256{}, C4{}, N1024{}, F{});
+                go(lat, m, C1{}, C2{}, C256{}, C2{}, N512{}, F{});
+                go(lat, m, C1{}, C2{}, C128{}, C4{}, N512{}, F{});
             } else {
-                go(lat, m, C2{}, C3{}, C256{}, C4{}, N512{});
-                go(lat, m, C1{}, C2{}, C256{}, C2{}, N512{});
+                go(lat, m, C2{}, C3{}, C256{}, C4{}, N512{}, F{});
+                go(lat, m, C1{}, C2{}, C256{}, C2{}, N512{}, F{});
             }
         }
         return hipSuccess;

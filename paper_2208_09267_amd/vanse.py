@@ -40,7 +40,7 @@ EXPORTS = [
     "vanse_batch_create", "vanse_batch_destroy", "vanse_batch_set_stream",
     "vanse_batch_set_tuning", "vanse_batch_step", "vanse_batch_autotune",
     "vanse_batch_last_error", "vanse_batch_update", "vanse_batch_two_step_layout",
-    "vanse_diagnostics_noalloc",
+    "vanse_diagnostics_noalloc", "vanse_batch_two_step_tiles",
 ]
 TUNE_NONTEMPORAL, TUNE_XCD_REMAP, TUNE_FLAT, TUNE_NT_STORES, TUNE_TWO_STEP = 1, 2, 4, 8, 16
 
@@ -107,6 +107,8 @@ def load_library(path: str = LIB_PATH):
             "vanse_batch_two_step_layout": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i)]),
             "vanse_batch_update": (i, [P, ctypes.POINTER(P), i]),
             "vanse_diagnostics_noalloc": (i, [i, I64P, P, P, i, P, P, P, P]),
+            "vanse_batch_two_step_tiles": (i, [P, i, ctypes.POINTER(i), ctypes.POINTER(i),
+                                               ctypes.POINTER(i)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -374,6 +376,14 @@ class Batch:
         rows, planes = (ctypes.c_int * n)(), (ctypes.c_int * n)()
         self._check(self.lib.vanse_batch_two_step_layout(self.h, n, rows, planes))
         return list(zip(rows, planes))
+
+    def two_step_tiles(self):
+        """[(cols, rows, planes)] per member of the two-step layout in effect
+        (cols = nx for tiles of full x-rows)."""
+        n = len(self.solvers)
+        cols, rows, planes = (ctypes.c_int * n)(), (ctypes.c_int * n)(), (ctypes.c_int * n)()
+        self._check(self.lib.vanse_batch_two_step_tiles(self.h, n, cols, rows, planes))
+        return list(zip(cols, rows, planes))
 
     def close(self):
         if getattr(self, "h", None):

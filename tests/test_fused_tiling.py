@@ -284,7 +284,11 @@ def test_two_step_tile_indexing_1024_threads(case):
 # x-split general tiles of the batched launch: (nx, ny, nz, rows, planes, cols)
 XT_CASES = [(192, 20, 9, 16, 4, 32), (192, 11, 7, 5, 3, 96), (130, 9, 6, 6, 5, 44),
             (129, 7, 5, 10, 2, 43), (256, 6, 4, 4, 4, 64), (100, 12, 3, 13, 2, 34),
-            (64, 8, 4, 8, 4, 64), (33, 5, 4, 5, 2, 33), (8, 5, 3, 2, 2, 3)]
+            (64, 8, 4, 8, 4, 64), (33, 5, 4, 5, 2, 33), (8, 5, 3, 2, 2, 3),
+            # the tiles the batched launch picks (FP64 192, 257, 360 wide;
+            # FP32 360 wide)
+            (192, 20, 9, 8, 4, 48), (257, 5, 4, 5, 4, 65), (360, 7, 5, 7, 2, 52),
+            (360, 7, 5, 7, 5, 72)]
 
 
 @pytest.mark.parametrize("lat", ["D3Q19"])

@@ -241,6 +241,36 @@ def test_two_step_batch_compile_time_tiles_bitwise(group, lat, dtype):
         s.close()
 
 
+def _full_rows(nx, ny, f64):
+    """Rows of a full-row general tile: 512 interior and 1024 (FP64: 512)
+    halo-plane cells per block."""
+    r = 512 // nx - 2 if f64 else min(512 // nx, 1024 // nx - 2)
+    r = min(r, ny)
+    return r if r >= 1 else 0
+
+
+def _xt_tile(nx, ny, f64):
+    """(columns, rows) of a member's general tile in a batch with x-split
+    members: full rows where they fit a block, else the split into k >= 2
+    segments of at least 48 columns (a halo column on each side) with the
+    most interior cells per loaded cell."""
+    full = _full_rows(nx, ny, f64)
+    if full:
+        return nx, full
+    best, best_c, best_r = 0.0, 0, 0
+    for k in range(2, 17):
+        c = -(-nx // k)
+        if c < 48:
+            break
+        r = min(512 // c, (512 if f64 else 1024) // (c + 2) - 2, ny)
+        if r < 1:
+            continue
+        e = c * r / ((c + 2) * (r + 2))
+        if e > best:
+            best, best_c, best_r = e, c, r
+    return best_c, best_r
+
+
 @pytest.mark.parametrize("dtype", [vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
 def test_two_step_batch_24_plane_segments_bitwise(dtype):
     """Four requests of the served stream's sizes (edges 80, 63, 153, 69:
@@ -262,7 +292,9 @@ def test_two_step_batch_24_plane_segments_bitwise(dtype):
     b = vanse.Batch(members)
     b.set_tuning(256, vanse.TUNE_TWO_STEP, 16)
     # rows: as many full x-rows as fit 512 interior and 1024 halo-plane cells
+    # (full rows fit every member, so none is split)
     assert b.two_step_layout() == [(6, 20), (8, 21), (3, 22), (7, 23)]
+    assert b.two_step_tiles() == [(80, 6, 20), (63, 8, 21), (153, 3, 22), (69, 7, 23)]
     b.step(steps)
     for k, s in enumerate(members):
         assert s.time == steps
@@ -313,3 +345,45 @@ def test_uniform_batch_of_one_128_cube_takes_shorter_segments_bitwise(dtype):
     assert np.array_equal(m.populations().cpu().numpy(), want)
     b.close()
     m.close()
+
+
+# members whose full x-rows do not fit a block (FP64: 192, 257 and 360
+# wide; FP32/FP16: 360 wide) make the batched two-step launch split their
+# x-rows into segments of 48 or more columns with a halo column on each side;
+# the other members keep full rows in the same launch
+XT_MEMBERS = [((192, 20, 9), 0.6, 11), ((160, 13, 7), 0.8, 12), ((130, 9, 6), 0.7, 13),
+              ((40, 12, 10), 0.9, 14), ((257, 5, 4), 0.66, 15), ((360, 7, 5), 0.75, 16)]
+
+
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("steps,chunk", [(37, 16), (10, 0)])
+def test_two_step_batch_x_split_tiles_bitwise(dtype, steps, chunk):
+    print("case", dtype, steps, chunk, flush=True)
+    f64 = dtype == vanse.FP64
+    pre = [0, 2, 0, 4, 2, 1]
+    solo = [_make(d, t, s, dtype, p) for (d, t, s), p in zip(XT_MEMBERS, pre)]
+    for s in solo:
+        s.step(steps)
+    want = [s.populations().cpu().numpy() for s in solo]
+    for s in solo:
+        s.close()
+    members = [_make(d, t, s, dtype, p) for (d, t, s), p in zip(XT_MEMBERS, pre)]
+    b = vanse.Batch(members)
+    b.set_tuning(128, vanse.TUNE_TWO_STEP, chunk)
+    tiles = b.two_step_tiles()
+    print("tiles", tiles, flush=True)
+    want_tiles = [_xt_tile(d[0], d[1], f64) for d, _, _ in XT_MEMBERS]
+    assert [(c, r) for c, r, _ in tiles] == want_tiles
+    split = [c < d[0] for (c, _, _), (d, _, _) in zip(tiles, XT_MEMBERS)]
+    assert split == ([True, False, False, False, True, True] if f64 else
+                     [False, False, False, False, False, True])
+    if not f64:
+        assert want_tiles[5] == (72, 7)
+    assert [(r, p) for _, r, p in tiles] == b.two_step_layout()
+    b.step(steps)
+    for k, s in enumerate(members):
+        assert s.time == pre[k] + steps
+        assert np.array_equal(s.populations().cpu().numpy(), want[k]), k
+    b.close()
+    for s in members:
+        s.close()
