@@ -257,6 +257,16 @@ constexpr int first_dir()
     return 0;
 }
 
+// sum_i R(w_i) - 1 for the weights as the collision rounds them (exact in
+// double: the terms are at most 27 floats within 8 binades).
+template <class L, class R>
+constexpr double weight_excess()
+{
+    double s = 0.0;
+    for (int i = 0; i < L::Q; ++i) s += (double)R(L::w[i]);
+    return s - 1.0;
+}
+
 template <class L, int MODE, class R>
 __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R omega,
                                         R fcoef, R Fex, R Fey, R Fez)
@@ -320,8 +330,20 @@ __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R o
     const R c3 = R(3) * omega * M0;
     const R d3 = R(3) * fcoef;
     {
+        // The collision conserves M0: sum_i W_i (P0 + ...) = P0 in exact
+        // arithmetic.  With the weights rounded to R their sum is 1 + delta
+        // (FP32 D3Q19: delta = 1.49e-8), which in the shifted modes, where
+        // P0 ~ omega (M0 - 1) is not small, would move the mass by delta P0
+        // per cell and step, always the same way.  The rest population takes
+        // back that excess (C0 P0).  FP64 stores f itself, and its weights'
+        // excess (about 1e-16) is left alone.
         constexpr R W0 = St::scaled ? R(1) : R(L::w[0]);
-        v[0] = om1 * v[0] + W0 * P0;
+        constexpr R C0 = St::shifted ? R(-weight_excess<L, R>() / (St::scaled ? L::w[0] : 1.0))
+                                     : R(0);
+        if constexpr (C0 != R(0))
+            v[0] = om1 * v[0] + W0 * P0 + C0 * P0;
+        else
+            v[0] = om1 * v[0] + W0 * P0;
     }
     static_for<1, H + 1>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
