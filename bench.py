@@ -4,8 +4,8 @@
 Workload (the headline configuration): D3Q19, 256^3 periodic, tau = 0.55,
 phi(x, t_n) = 0.75 + cos(2 pi n / 1000) * dphi(x) with dphi the seeded sum of
 8 Fourier modes (seed 1), Taylor-Green initial velocity of amplitude 0.02,
-rho = 1.  Storage variants: FP32 shifted populations (headline), FP64 and
-FP16 shifted.  One "step" is one full time step of the whole lattice; the
+rho = 1.  Storage variants: FP32 shifted populations (headline), FP64, FP16
+shifted and FX16 shifted (16-bit fixed point).  One "step" is one full time step of the whole lattice; the
 state is resident in HBM before timing starts.
 
 Prints ONE JSON line (rank 0).  `value` is the headline variant's MLUPS;
@@ -33,16 +33,17 @@ PEAK_HBM_GBS = 8000.0
 # (one lattice update per cell for the single-step kernel, two for the
 # two-step kernel)
 BYTES_PER_PASS = {"fp64": 19 * 8 * 2 + 8, "fp32_shifted": 19 * 4 * 2 + 4,
-                  "fp16_shifted": 19 * 2 * 2 + 4}
-DTYPE_NAME = {"fp64": "f64", "fp32_shifted": "f32", "fp16_shifted": "f32"}
-MODE_NAME = {"fp64": "FP64", "fp32_shifted": "FP32_SHIFTED", "fp16_shifted": "FP16_SHIFTED"}
+                  "fp16_shifted": 19 * 2 * 2 + 4, "fx16_shifted": 19 * 2 * 2 + 4}
+DTYPE_NAME = {"fp64": "f64", "fp32_shifted": "f32", "fp16_shifted": "f32", "fx16_shifted": "f32"}
+MODE_NAME = {"fp64": "FP64", "fp32_shifted": "FP32_SHIFTED", "fp16_shifted": "FP16_SHIFTED",
+             "fx16_shifted": "FX16_SHIFTED"}
 
 
 def kernel_name(variant, rows, lattice="D3Q19"):
     """Label of the kernel a launch shape runs (two-step rows 0: single step);
     the same labels key the committed counter record."""
     from paper_2208_09267_amd.rocprof_summary import kernel_label
-    mode = {"fp64": 0, "fp32_shifted": 1, "fp16_shifted": 2}[variant]
+    mode = {"fp64": 0, "fp32_shifted": 1, "fp16_shifted": 2, "fx16_shifted": 3}[variant]
     return kernel_label("fused2_kernel" if rows else "step_kernel", lattice, mode, rows or None)
 
 
@@ -69,9 +70,9 @@ def measured_traffic(variant, kernel):
 # --fixed-launch, e.g. under a counter profiler that perturbs timing)
 # (tile_x, tile_y, flat, two-step rows, two-step planes)
 FIXED_LAUNCH = {"fp32_shifted": (1024, 1, True, 4, 64), "fp64": (512, 1, True, 2, 128),
-                "fp16_shifted": (256, 4, False, 4, 64)}
+                "fp16_shifted": (256, 4, False, 4, 64), "fx16_shifted": (256, 4, False, 4, 64)}
 SINGLE_LAUNCH = {"fp32_shifted": (1024, 1, True, 0, 0), "fp64": (512, 1, True, 0, 0),
-                 "fp16_shifted": (256, 4, False, 0, 0)}
+                 "fp16_shifted": (256, 4, False, 0, 0), "fx16_shifted": (256, 4, False, 0, 0)}
 
 
 def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
@@ -139,7 +140,7 @@ def gpu_variant(variant, w, pert_t, u0_t, steps, warmup, fixed_launch=False):
 
 
 Q_OF = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
-ELEM = {"fp64": (8, 8), "fp32_shifted": (4, 4), "fp16_shifted": (2, 4)}
+ELEM = {"fp64": (8, 8), "fp32_shifted": (4, 4), "fp16_shifted": (2, 4), "fx16_shifted": (2, 4)}
 
 
 def solo_run(w, variant, steps, warmup=30):
@@ -292,7 +293,7 @@ def _solve_fields(w, dtype, progress=None):
 
 
 def precision_study():
-    """Error of the FP32- and FP16-shifted storage modes against the FP64
+    """Error of the FP32-, FP16- and FX16-shifted storage modes against the FP64
     path (which matches the CPU oracle to <= 1e-11) on the D3Q19 256^3
     workload after 2000 steps, next to the FP64 discretisation error at the
     same resolution, estimated against a 512^3 FP64 run of the same physical
@@ -311,7 +312,7 @@ def precision_study():
     n = w.dims[0]
     ref = {}
     for name, dt in (("fp64", vanse.FP64), ("fp32_shifted", vanse.FP32_SHIFTED),
-                     ("fp16_shifted", vanse.FP16_SHIFTED)):
+                     ("fp16_shifted", vanse.FP16_SHIFTED), ("fx16_shifted", vanse.FX16_SHIFTED)):
         ref[name] = _solve_fields(w, dt, progress=name)
     w2 = dataclasses.replace(w, name="D3Q19 512^3 reference", dims=(2 * n,) * 3,
                              steps=4 * w.steps, period=4 * w.period, tgv_amp=w.tgv_amp / 2)
@@ -350,7 +351,7 @@ def precision_study():
                                                                  "p": float(g["norms"][1]),
                                                                  "u": float(g["norms"][2])},
             "abs_error": vs}
-    for name in ("fp32_shifted", "fp16_shifted"):
+    for name in ("fp32_shifted", "fp16_shifted", "fx16_shifted"):
         r, p, u = ref[name]
         err = {"rho": r - r64, "p": p - p64, "u": (u - u64).norm(dim=0),
                "p_meanfree": (p - p.mean()) - (p64 - p64.mean())}
@@ -505,7 +506,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--variants", default="fp32_shifted,fp64,fp16_shifted",
+    ap.add_argument("--variants", default="fp32_shifted,fp64,fp16_shifted,fx16_shifted",
                     help="comma list; the first one is the headline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -516,7 +517,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched workloads and the served sample")
     ap.add_argument("--no-serve", action="store_true",
-                    help="skip the served sample (a 15 s window of requests at 8/s)")
+                    help="skip the served samples (30 s of requests at 20/s, 15 s at 8/s)")
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--no-d3q27", action="store_true")
     ap.add_argument("--no-single-step", action="store_true",
@@ -526,7 +527,7 @@ def main():
     ap.add_argument("--fixed-shape", action="append", default=[],
                     help="with --fixed-launch: VARIANT=tile_x,tile_y,flat,rows,planes")
     ap.add_argument("--precision", action="store_true",
-                    help="run the FP32/FP16 error study instead of the throughput bench")
+                    help="run the reduced-storage error study instead of the throughput bench")
     ap.add_argument("--serve", action="store_true",
                     help="run the served request stream instead of the throughput bench")
     ap.add_argument("--rate", type=float, default=20.0)

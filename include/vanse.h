@@ -56,9 +56,19 @@ enum { VANSE_QUAD_NONE = 8 };
 
 /* Population storage.  FP64: f_i in binary64, FP64 arithmetic.
  * FP32_SHIFTED: g_i = f_i - w_i in binary32, FP32 arithmetic in deviation
- * form.  FP16_SHIFTED: h_i = (f_i - w_i)/w_i in binary16, FP32 arithmetic.
- * In the reduced modes eps_pert is held in binary32. */
-enum { VANSE_FP64 = 0, VANSE_FP32_SHIFTED = 1, VANSE_FP16_SHIFTED = 2 };
+ * form.  FP16_SHIFTED: h_i = f_i / (c w_i) - 1 in binary16, FP32
+ * arithmetic.  FX16_SHIFTED: the same h_i in 16-bit fixed point,
+ * round(2^15 h_i) as int16, FP32 arithmetic: it holds 0 < f_i < 2 c w_i
+ * with a rounding error of at most 2^-16 c w_i, where binary16 keeps 11
+ * bits of h_i; a value at the bound of that range (a negative population,
+ * or one above twice the mean-mass equilibrium) reads back as NaN and
+ * vanse_diagnostics then reports EUNSTABLE.  c, the unit of both 16-bit
+ * codes, is the mean of rho0 phi over the cells at vanse_init (the
+ * conserved mass per cell, rounded to binary32), so that h_i carries only
+ * the relative deviations of M0 and u from their means; these modes step
+ * in units of c, with the forces divided by c.  In the reduced modes
+ * eps_pert is held in binary32. */
+enum { VANSE_FP64 = 0, VANSE_FP32_SHIFTED = 1, VANSE_FP16_SHIFTED = 2, VANSE_FX16_SHIFTED = 3 };
 
 enum {
     VANSE_OK = 0,
@@ -75,7 +85,8 @@ enum {
  *            nx*ny*nz < 2^31
  *   tau      BGK relaxation time, finite and > 1/2 (eq. lbe; the recovered
  *            viscosity is nu = (tau - 1/2) c_s^2)
- *   dtype    VANSE_FP64, VANSE_FP32_SHIFTED or VANSE_FP16_SHIFTED
+ *   dtype    VANSE_FP64, VANSE_FP32_SHIFTED, VANSE_FP16_SHIFTED or
+ *            VANSE_FX16_SHIFTED
  *   out      receives the handle
  * Allocates the single in-place population array (AA pattern), the phi
  * perturbation copy and the reduction scratch with hipMalloc; all are freed
@@ -122,7 +133,10 @@ int vanse_set_force_field(vanse_t h, const double *F);
 /* Initial populations (eq. equilibrium): f_i = f_i^eq of M0 = rho0 phi(x, 0)
  * and u0, with no non-equilibrium part.  rho0: device FP64 [ncells] or NULL
  * (1); u0: device FP64 SoA [d][ncells] or NULL (0).  Resets the time to 0.
- * Requires vanse_set_porosity.  Errors: ESTATE, EDEVICE. */
+ * The 16-bit modes first reduce rho0 phi to the unit c of their encoding
+ * and synchronise (EINVAL if its mean is not finite and > 0; the solver is
+ * then left as it was).  Requires vanse_set_porosity.  Errors: ESTATE,
+ * EINVAL, EDEVICE. */
 int vanse_init(vanse_t h, const double *rho0, const double *u0);
 
 /* Advance n >= 0 time steps (asynchronous).  Errors: ESTATE, EINVAL,
@@ -137,8 +151,9 @@ int vanse_moments(vanse_t h, double *rho, double *p, double *u);
 /* Global FP64 sums at t_n, in a fixed (deterministic) order, written to the
  * HOST array out[7]: out[0] = sum_x sum_i f_i (the phi-weighted mass
  * sum rho I), out[1..3] = sum_x sum_i xi_i f_i, out[4..6] = sum_x F.
- * Synchronises.  A non-finite sum makes h sticky-unstable: this and every
- * later vanse_step return EUNSTABLE. */
+ * Synchronises.  A non-finite sum (in FX16_SHIFTED also a population at the
+ * bound of its range) makes h sticky-unstable: this and every later
+ * vanse_step return EUNSTABLE. */
 int vanse_diagnostics(vanse_t h, double out[7]);
 
 /* Populations f_i(x, t_n) in FP64, natural order, SoA [Q][ncells] in this

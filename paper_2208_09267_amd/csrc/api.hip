@@ -78,10 +78,17 @@ StepArgs step_args(const Solver &s, int64_t n)
     a.f = s.f;
     a.pert = s.pert;
     a.eps_mean = s.eps_mean;
+    a.shift = s.shift;
     a.m = modulation(n, s.period);
     a.omega = 1.0 / s.tau;
     a.fcoef = 1.0 - 0.5 * a.omega;
-    for (int d = 0; d < 3; ++d) a.F[d] = s.F[d];
+    // the 16-bit modes step in units of c (a mass scale): forces divided by c
+    const bool unit_c = s.mode == MODE_F16S || s.mode == MODE_FX16S;
+    a.fscale = unit_c ? 1.0 / s.shift : 1.0;
+    for (int d = 0; d < 3; ++d) {
+        a.F[d] = s.F[d];
+        a.Fk[d] = s.F[d] * a.fscale;
+    }
     a.force = s.force_on ? s.force : nullptr;
     int n_axes = 0;
     for (int b = 0; b < 3; ++b) n_axes += (s.qmask >> b) & 1;
@@ -182,7 +189,8 @@ int vanse_create(int lattice, const int64_t dims[3], double tau, int dtype, vans
     *out = nullptr;
     if (lattice != VANSE_D2Q9 && lattice != VANSE_D3Q19 && lattice != VANSE_D3Q27)
         return fail(nullptr, VANSE_EINVAL, "vanse_create: unknown lattice");
-    if (dtype != VANSE_FP64 && dtype != VANSE_FP32_SHIFTED && dtype != VANSE_FP16_SHIFTED)
+    if (dtype != VANSE_FP64 && dtype != VANSE_FP32_SHIFTED && dtype != VANSE_FP16_SHIFTED &&
+        dtype != VANSE_FX16_SHIFTED)
         return fail(nullptr, VANSE_EINVAL, "vanse_create: unknown dtype");
     if (!dims) return fail(nullptr, VANSE_EINVAL, "vanse_create: dims is NULL");
     for (int a = 0; a < 3; ++a)
@@ -367,8 +375,24 @@ int vanse_init(vanse_t h, const double *rho0, const double *u0)
     if (!h) return fail(nullptr, VANSE_EINVAL, "vanse_init: NULL handle");
     Solver &s = h->s;
     if (!s.porosity_set) return fail(&s, VANSE_ESTATE, "vanse_init: call vanse_set_porosity first");
-    hipError_t e = vanse::launch_init(s, rho0, u0);
+    hipError_t e;
+    if (s.mode == vanse::MODE_F16S || s.mode == vanse::MODE_FX16S) {
+        // unit of the 16-bit encodings: the mean initial M0, rounded to FP32
+        double *res = s.scratch + 7 * vanse::kReduceBlocks;
+        double sum = 0.0;
+        e = vanse::launch_init_mass(s, rho0, res);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&sum, res, sizeof(double), hipMemcpyDeviceToHost, s.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s.stream);
+        if (e != hipSuccess) return hip_fail(&s, e, "vanse_init");
+        const double c = (double)(float)(sum / s.geo.ncells);
+        if (!std::isfinite(c) || !(c > 0.0))
+            return fail(&s, VANSE_EINVAL, "vanse_init: the mean of rho0 phi is not finite and > 0");
+        s.shift = c;
+    }
+    e = vanse::launch_init(s, rho0, u0);
     if (e != hipSuccess) return hip_fail(&s, e, "vanse_init");
+    ++s.gen;  // a batch holding this solve refreshes its step parameters (the unit c)
     s.t = 0;
     s.initialized = true;
     s.unstable = false;

@@ -9,7 +9,7 @@
 
 namespace vanse {
 
-enum Mode { MODE_F64 = 0, MODE_F32S = 1, MODE_F16S = 2 };
+enum Mode { MODE_F64 = 0, MODE_F32S = 1, MODE_F16S = 2, MODE_FX16S = 3 };
 
 // Launch-time view of one lattice: sizes and the population plane stride
 // (elements between direction planes of the SoA population array).
@@ -42,10 +42,13 @@ struct StepArgs {
     void *f;             // populations, SoA [Q][stride], storage type of the mode
     const void *pert;    // phi perturbation, double (FP64) or float (reduced)
     double eps_mean;     // phi = eps_mean + m * pert
+    double shift;        // 16-bit modes: the unit c of the stored f_i / (c w_i) - 1
     double m;            // modulation m(n) of the current step
     double omega;        // 1 / tau
     double fcoef;        // 1 - omega / 2 (Guo forcing prefactor)
     double F[3];         // constant external force density
+    double Fk[3];        // the same in the step kernels' units (16-bit modes: F / c)
+    double fscale;       // per-cell force to the step kernels' units (16-bit modes: 1 / c)
     const void *force;   // optional per-cell force density, SoA [d][stride] (R), or null
     double wq;           // quadrature weight varpi_{i != 0}
     double n2;           // 2 * (number of quadrature axes)
@@ -85,6 +88,7 @@ struct Solver {
     Geometry geo{};
     double tau = 0.0;
     double eps_mean = 1.0, period = 0.0;
+    double shift = 1.0;          // 16-bit modes: unit c of the encoding, set by vanse_init
     int qmask = 0;
     double F[3] = {0.0, 0.0, 0.0};
     bool porosity_set = false, initialized = false, unstable = false;
@@ -171,6 +175,10 @@ bool fused_shape(int lattice, int mode, const Geometry &g, int rows, FusedShape 
 size_t fused_lds_bytes(int q, int mode, int nx, int rows);
 hipError_t launch_fused(const Solver &s, const StepArgs &a);
 hipError_t launch_init(const Solver &s, const double *rho0, const double *u0);
+// sum over cells of rho0 phi(x, 0) (the initial M0; rho0 NULL: 1), FP64, in
+// the fixed order of the reductions, into out_dev[0] (device); uses the
+// solver's reduction scratch.
+hipError_t launch_init_mass(const Solver &s, const double *rho0, double *out_dev);
 hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, unsigned block,
                              const BatchMember *members, const unsigned *owner,
                              const double *mtab, const long long *t0, int j, int count,

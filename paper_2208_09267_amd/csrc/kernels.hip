@@ -62,42 +62,72 @@ __device__ __forceinline__ R dot3(R x, R y, R z)
 }
 
 // Storage of one population: T is the raw element type in HBM, R the
-// arithmetic type, and `shifted` / `scaled` say what the stored value v_i is:
+// arithmetic type, and `shifted` / `scaled` / `unit_c` say what the stored
+// value v_i is:
 //   FP64        v_i = f_i                     (T = double)
 //   FP32 shift  v_i = f_i - w_i               (T = float)
-//   FP16 shift  v_i = (f_i - w_i) / w_i       (T = binary16 bits, decoded to float)
+//   FP16 shift  v_i = f_i / (c w_i) - 1       (T = binary16 bits, decoded to float)
+//   FX16 shift  v_i = f_i / (c w_i) - 1       (T = int16 bits: 2^15 v_i rounded to
+//                                              nearest, saturated at +-32767)
+// c is the solve's mean M0 at initialisation (StepArgs::shift): sum_i f_i is
+// conserved, so v_i stays of the size of the relative deviations of M0 and u
+// from their means, which the 16-bit codes resolve best near 0 (FP16: 11
+// significant bits) or uniformly over 0 < f_i < 2 c w_i (FX16: rounding
+// error at most 2^-16 c w_i).  The 16-bit modes step in units of c: their
+// M0 is sum f / c, and the forces enter divided by c (StepArgs::Fk, fscale);
+// u is the same in any unit of mass.
 template <int MODE> struct Storage;
 template <> struct Storage<MODE_F64> {
     using T = double;
     using R = double;
-    static constexpr bool shifted = false, scaled = false;
+    static constexpr bool shifted = false, scaled = false, unit_c = false;
     static __device__ __forceinline__ R decode(T v) { return v; }
     static __device__ __forceinline__ T encode(R v) { return v; }
 };
 template <> struct Storage<MODE_F32S> {
     using T = float;
     using R = float;
-    static constexpr bool shifted = true, scaled = false;
+    static constexpr bool shifted = true, scaled = false, unit_c = false;
     static __device__ __forceinline__ R decode(T v) { return v; }
     static __device__ __forceinline__ T encode(R v) { return v; }
 };
 template <> struct Storage<MODE_F16S> {
     using T = unsigned short;
     using R = float;
-    static constexpr bool shifted = true, scaled = true;
+    static constexpr bool shifted = true, scaled = true, unit_c = true;
     static __device__ __forceinline__ R decode(T v) { return __half2float(__ushort_as_half(v)); }
     static __device__ __forceinline__ T encode(R v) { return __half_as_ushort(__float2half_rn(v)); }
 };
+template <> struct Storage<MODE_FX16S> {
+    using T = unsigned short;
+    using R = float;
+    static constexpr bool shifted = true, scaled = true, unit_c = true;
+    static __device__ __forceinline__ R decode(T v) { return float((short)v) * (1.0f / 32768.0f); }
+    // round to nearest even, then saturate (a NaN saturates too: fmaxf
+    // returns the other operand), so that an out-of-range value reads back
+    // at the bound, which to_f64 reports as not a number
+    static __device__ __forceinline__ T encode(R v)
+    {
+        const float q = fminf(fmaxf(rintf(v * 32768.0f), -32767.0f), 32767.0f);
+        return (unsigned short)(short)(int)q;
+    }
+};
 
-// FP64 value of f_i from a stored population (off the hot path).
+// FP64 value of f_i from a stored population (off the hot path); c: the
+// unit of the 16-bit modes.  An FX16 value at the bound of its range (the
+// state left the range, or a NaN was stored) reads as NaN.
 template <class L, int MODE, int I>
-__device__ __forceinline__ double to_f64(typename Storage<MODE>::T raw)
+__device__ __forceinline__ double to_f64(typename Storage<MODE>::T raw, double c)
 {
     using St = Storage<MODE>;
+    if constexpr (MODE == MODE_FX16S) {
+        if (raw == 0x7fffu || raw == 0x8000u || raw == 0x8001u) return __builtin_nan("");
+    }
     const double v = double(St::decode(raw));
     if constexpr (!St::shifted) return v;
     else if constexpr (!St::scaled) return L::w[I] + v;
-    else return L::w[I] + L::w[I] * v;
+    else if constexpr (!St::unit_c) return L::w[I] + L::w[I] * v;
+    else return c * L::w[I] + c * L::w[I] * v;
 }
 
 // Unsigned division by a launch-invariant divisor d >= 1 for dividends
@@ -236,7 +266,7 @@ __device__ __forceinline__ void eps_ops(const R *__restrict__ pert, R eps_mean, 
 // v[Q] (f_i, f_i - w_i, or (f_i - w_i)/w_i by storage mode).
 //
 // Per cell: M0 = sum f (= 1 + sum (f - w) in the shifted modes, since
-// sum w = 1 and sum w xi = 0), rho = M0/I (eq. density), p = rho/3,
+// sum w = 1 and sum w xi = 0; the 16-bit modes in units of c), rho = M0/I (eq. density), p = rho/3,
 // F = p grad(phi) + F_ext (eq. pressForce), u = (j + F/2)/M0 (eq. velocity).
 // The update f - (f - f^eq)/tau + Omega^F (eq. lbe with eq. feq, rho I = M0,
 // and Guo's forcing term) is evaluated for each pair of opposite directions
@@ -265,6 +295,15 @@ constexpr double weight_excess()
     double s = 0.0;
     for (int i = 0; i < L::Q; ++i) s += (double)R(L::w[i]);
     return s - 1.0;
+}
+
+// F + Fc for a per-cell force value Fc stored in physical units: divided by c
+// (times fscale = 1/c) in the 16-bit modes, which step in units of c.
+template <class St, class R>
+__device__ __forceinline__ R add_force(R F, R Fc, double fscale)
+{
+    if constexpr (St::unit_c) return F + R(fscale) * Fc;
+    else return F + Fc;
 }
 
 template <class L, int MODE, class R>
@@ -300,12 +339,12 @@ __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R o
         }
     });
     const R M0 = St::shifted ? R(1) + s0 : s0;
-    // eq. density and the 1/M0 of eq. velocity.  In FP16 storage, whose
+    // eq. density and the 1/M0 of eq. velocity.  In the 16-bit modes, whose
     // rounding dominates the error, the hardware reciprocal (about 1 ulp of
-    // FP32) replaces the two correctly rounded divisions: the FP16 step is
-    // bound by its arithmetic, of which they are about a tenth.
+    // FP32) replaces the two correctly rounded divisions: their step is bound
+    // by its arithmetic, of which they are about a tenth.
     R rho, inv;
-    if constexpr (MODE == MODE_F16S) {
+    if constexpr (St::scaled) {
         rho = M0 * __builtin_amdgcn_rcpf(I);
         inv = __builtin_amdgcn_rcpf(M0);
     } else {
@@ -413,13 +452,15 @@ __device__ __forceinline__ void cell_step(const StepArgs &a, int x, int y, int z
     R I, gx, gy, gz;
     eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
 
-    R Fex = R(a.F[0]), Fey = R(a.F[1]), Fez = R(a.F[2]);
+    R Fex = R(a.Fk[0]), Fey = R(a.Fk[1]), Fez = R(a.Fk[2]);
     if (a.force) {  // per-cell force density, SoA [d][stride] (wave-uniform branch)
         const R *__restrict__ fc = static_cast<const R *>(a.force);
         const unsigned off = (unsigned)X[1] * (unsigned)sizeof(R);
-        Fex = Fex + ld<R, false>(fc + (Zo[1] + Yo[1]), off);
-        Fey = Fey + ld<R, false>(fc + a.geo.stride + (Zo[1] + Yo[1]), off);
-        if constexpr (L::D == 3) Fez = Fez + ld<R, false>(fc + 2 * a.geo.stride + (Zo[1] + Yo[1]), off);
+        Fex = add_force<St>(Fex, ld<R, false>(fc + (Zo[1] + Yo[1]), off), a.fscale);
+        Fey = add_force<St>(Fey, ld<R, false>(fc + a.geo.stride + (Zo[1] + Yo[1]), off), a.fscale);
+        if constexpr (L::D == 3)
+            Fez = add_force<St>(Fez, ld<R, false>(fc + 2 * a.geo.stride + (Zo[1] + Yo[1]), off),
+                                a.fscale);
     }
     collide<L, MODE, R>(v, I, gx, gy, gz, R(a.omega), R(a.fcoef), Fex, Fey, Fez);
 
@@ -656,19 +697,19 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         e[6] = phi_of(em, mm, rm[r * RW + c]);
         R I, gx, gy, gz;
         eps_combine<L, R>(e, R(a.wq), R(a.n2), a.qmask, I, gx, gy, gz);
-        R Fex = R(a.F[0]), Fey = R(a.F[1]), Fez = R(a.F[2]);
+        R Fex = R(a.Fk[0]), Fey = R(a.Fk[1]), Fez = R(a.Fk[2]);
         if (fc) {
             if constexpr (GEN) {
                 const unsigned o = boff(z * nxy + y * nx + x, sizeof(R));
-                Fex = Fex + ld<R, false>(fc, o);
-                Fey = Fey + ld<R, false>(fc + S, o);
-                Fez = Fez + ld<R, false>(fc + 2 * S, o);
+                Fex = add_force<St>(Fex, ld<R, false>(fc, o), a.fscale);
+                Fey = add_force<St>(Fey, ld<R, false>(fc + S, o), a.fscale);
+                Fez = add_force<St>(Fez, ld<R, false>(fc + 2 * S, o), a.fscale);
             } else {
                 const R *row = fc + (z * nxy + y * nx);
                 const unsigned ox = (unsigned)x * (unsigned)sizeof(R);
-                Fex = Fex + ld<R, false>(row, ox);
-                Fey = Fey + ld<R, false>(row + S, ox);
-                Fez = Fez + ld<R, false>(row + 2 * S, ox);
+                Fex = add_force<St>(Fex, ld<R, false>(row, ox), a.fscale);
+                Fey = add_force<St>(Fey, ld<R, false>(row + S, ox), a.fscale);
+                Fez = add_force<St>(Fez, ld<R, false>(row + 2 * S, ox), a.fscale);
             }
         }
         collide<L, MODE, R>(v, I, gx, gy, gz, R(a.omega), R(a.fcoef), Fex, Fey, Fez);
@@ -923,7 +964,7 @@ __device__ __forceinline__ void load_natural(const StepArgs &a, const Cell &k, i
             raw = f[i * S + k.c];
         else
             raw = f[opp<L>(i) * S + k.at(-L::cx[i], -L::cy[i], -L::cz[i])];
-        fo[i] = to_f64<L, MODE, i>(raw);
+        fo[i] = to_f64<L, MODE, i>(raw, a.shift);
     });
 }
 
@@ -1024,7 +1065,7 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double *__r
         else if constexpr (!Storage<MODE>::scaled)
             f[i * a.geo.stride + c] = Storage<MODE>::encode(R(feq - L::w[i]));
         else
-            f[i * a.geo.stride + c] = Storage<MODE>::encode(R((feq - L::w[i]) / L::w[i]));
+            f[i * a.geo.stride + c] = Storage<MODE>::encode(R(feq / (a.shift * L::w[i]) - 1.0));
     });
 }
 
@@ -1068,6 +1109,22 @@ __global__ void __launch_bounds__(kReduceThreads) diag_kernel(StepArgs a, int pa
         }
     }
     block_reduce<7>(acc, partials + 7 * blockIdx.x);
+}
+
+// sum over cells of rho0 phi(x, 0), phi formed in R as init_kernel forms it
+// (the mean initial M0 is the unit of the 16-bit encodings)
+template <class R>
+__global__ void __launch_bounds__(kReduceThreads) init_mass_kernel(StepArgs a,
+                                                                   const double *__restrict__ rho0,
+                                                                   double *__restrict__ partials)
+{
+    double acc[1] = {0.0};
+    for (int c = blockIdx.x * kReduceThreads + threadIdx.x; c < a.geo.ncells;
+         c += gridDim.x * kReduceThreads) {
+        const R e = R(a.eps_mean) + R(a.m) * static_cast<const R *>(a.pert)[c];
+        acc[0] += (rho0 ? rho0[c] : 1.0) * double(e);
+    }
+    block_reduce<1>(acc, partials + blockIdx.x);
 }
 
 template <int NV>
@@ -1148,7 +1205,8 @@ static hipError_t dispatch(int lattice, int mode, Fn &&fn)
     auto by_mode = [&](auto lat) {
         if (mode == MODE_F64) return fn(lat, std::integral_constant<int, MODE_F64>{});
         if (mode == MODE_F32S) return fn(lat, std::integral_constant<int, MODE_F32S>{});
-        return fn(lat, std::integral_constant<int, MODE_F16S>{});
+        if (mode == MODE_F16S) return fn(lat, std::integral_constant<int, MODE_F16S>{});
+        return fn(lat, std::integral_constant<int, MODE_FX16S>{});
     };
     if (lattice == 0) return by_mode(D2Q9{});
     if (lattice == 1) return by_mode(D3Q19{});
@@ -1309,7 +1367,8 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
     auto modes = [&](auto lat) {
         if (s.mode == MODE_F64) shapes(lat, std::integral_constant<int, MODE_F64>{});
         else if (s.mode == MODE_F32S) shapes(lat, std::integral_constant<int, MODE_F32S>{});
-        else shapes(lat, std::integral_constant<int, MODE_F16S>{});
+        else if (s.mode == MODE_F16S) shapes(lat, std::integral_constant<int, MODE_F16S>{});
+        else shapes(lat, std::integral_constant<int, MODE_FX16S>{});
     };
     if (s.lattice == 1) modes(D3Q19{});
     else modes(D3Q27{});
@@ -1499,6 +1558,20 @@ hipError_t launch_init(const Solver &s, const double *rho0, const double *u0)
     });
 }
 
+hipError_t launch_init_mass(const Solver &s, const double *rho0, double *out_dev)
+{
+    StepArgs a = step_args(s, 0);
+    double *partials = s.scratch;
+    if (s.mode == MODE_F64)
+        init_mass_kernel<double><<<kReduceBlocks, kReduceThreads, 0, s.stream>>>(a, rho0, partials);
+    else
+        init_mass_kernel<float><<<kReduceBlocks, kReduceThreads, 0, s.stream>>>(a, rho0, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    finalize_kernel<1><<<1, kReduceThreads, 0, s.stream>>>(partials, kReduceBlocks, out_dev);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments(const Solver &s, int parity, double m, double *rho, double *p,
                           double *u)
 {
@@ -1595,10 +1668,12 @@ hipError_t launch_diagnostics_noalloc(int lattice, const Geometry &g, const doub
     a.f = const_cast<double *>(f);
     a.pert = phi;
     a.eps_mean = 0.0;
+    a.shift = 1.0;
     a.m = 1.0;
     a.omega = 1.0;
     a.fcoef = 0.5;
-    for (int d = 0; d < 3; ++d) a.F[d] = F[d];
+    for (int d = 0; d < 3; ++d) a.F[d] = a.Fk[d] = F[d];
+    a.fscale = 1.0;
     a.force = force;
     a.wq = wq;
     a.n2 = n2;

@@ -35,8 +35,8 @@ from . import vanse
 from . import workloads as W
 
 _Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
-_ELEM = {vanse.FP64: 8, vanse.FP32_SHIFTED: 4, vanse.FP16_SHIFTED: 2}
-_PERT = {vanse.FP64: 8, vanse.FP32_SHIFTED: 4, vanse.FP16_SHIFTED: 4}
+_ELEM = {vanse.FP64: 8, vanse.FP32_SHIFTED: 4, vanse.FP16_SHIFTED: 2, vanse.FX16_SHIFTED: 2}
+_PERT = {vanse.FP64: 8, vanse.FP32_SHIFTED: 4, vanse.FP16_SHIFTED: 4, vanse.FX16_SHIFTED: 4}
 
 
 def state_bytes(lattice: str, dims, dtype: int, two_step: bool = False) -> int:

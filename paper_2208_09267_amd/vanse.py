@@ -23,9 +23,10 @@ LIB_PATH = os.path.join(HERE, "libvanse.so")
 
 D2Q9, D3Q19, D3Q27 = 0, 1, 2
 QUAD_NONE = 8
-FP64, FP32_SHIFTED, FP16_SHIFTED = 0, 1, 2
+FP64, FP32_SHIFTED, FP16_SHIFTED, FX16_SHIFTED = 0, 1, 2, 3
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
-DTYPES = {"fp64": FP64, "fp32_shifted": FP32_SHIFTED, "fp16_shifted": FP16_SHIFTED}
+DTYPES = {"fp64": FP64, "fp32_shifted": FP32_SHIFTED, "fp16_shifted": FP16_SHIFTED,
+          "fx16_shifted": FX16_SHIFTED}
 LATTICES = {"D2Q9": D2Q9, "D3Q19": D3Q19, "D3Q27": D3Q27}
 
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE",

@@ -30,10 +30,13 @@ def test_more_than_one_gpu_exits_with_a_message():
      "fused2_kernel<D3Q19, FP64, rows 2>"),
     ("void vanse::step_kernel<vanse::D3Q19, 2, 1, true, 0>(vanse::StepArgs)",
      "step_kernel<D3Q19, FP16_SHIFTED>"),
+    ("void vanse::fused2_kernel<vanse::D3Q19, 3, 1, 2, 256, 4, false, 1024>(vanse::StepArgs)",
+     "fused2_kernel<D3Q19, FX16_SHIFTED, rows 4>"),
 ])
 def test_rocprof_names_map_to_bench_labels(full, label):
     assert rs.parse_name(full)[0] == label
-    variant = {0: "fp64", 1: "fp32_shifted", 2: "fp16_shifted"}[rs.parse_name(full)[2]]
+    variant = {0: "fp64", 1: "fp32_shifted", 2: "fp16_shifted",
+               3: "fx16_shifted"}[rs.parse_name(full)[2]]
     rows = 4 if "rows 4" in label else (2 if "rows 2" in label else 0)
     assert bench.kernel_name(variant, rows) == label
 

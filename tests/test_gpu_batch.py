@@ -28,7 +28,8 @@ def _make(dims, tau, seed, dtype, pre_steps=0):
     return s
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED,
+                                   vanse.FX16_SHIFTED])
 @pytest.mark.parametrize("steps,chunk", [(37, 16), (5, 0), (32, 16)])
 def test_batch_matches_solo_bitwise(dtype, steps, chunk):
     print("case", dtype, steps, chunk, flush=True)
@@ -120,7 +121,8 @@ def test_batch_update_changes_members_and_stays_bitwise():
         s.close()
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED,
+                                   vanse.FX16_SHIFTED])
 @pytest.mark.parametrize("steps,chunk", [(37, 16), (10, 0), (32, 16)])
 def test_two_step_batch_matches_solo_bitwise(dtype, steps, chunk):
     """Members at even levels advance by two-step launches (general tiles for
@@ -215,7 +217,8 @@ def _make_lat(lat, dims, tau, seed, dtype, pre_steps=0):
     return s
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED,
+                                   vanse.FX16_SHIFTED])
 @pytest.mark.parametrize("lat", ["D3Q19", "D3Q27"])
 @pytest.mark.parametrize("group", list(TILE_GROUPS))
 def test_two_step_batch_compile_time_tiles_bitwise(group, lat, dtype):
@@ -271,7 +274,7 @@ def _xt_tile(nx, ny, f64):
     return best_c, best_r
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP32_SHIFTED, vanse.FP16_SHIFTED, vanse.FX16_SHIFTED])
 def test_two_step_batch_24_plane_segments_bitwise(dtype):
     """Four requests of the served stream's sizes (edges 80, 63, 153, 69:
     4.7 M cells) have too few general tiles to fill the GPU with 32-plane
@@ -355,7 +358,8 @@ XT_MEMBERS = [((192, 20, 9), 0.6, 11), ((160, 13, 7), 0.8, 12), ((130, 9, 6), 0.
               ((40, 12, 10), 0.9, 14), ((257, 5, 4), 0.66, 15), ((360, 7, 5), 0.75, 16)]
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED,
+                                   vanse.FX16_SHIFTED])
 @pytest.mark.parametrize("steps,chunk", [(37, 16), (10, 0)])
 def test_two_step_batch_x_split_tiles_bitwise(dtype, steps, chunk):
     print("case", dtype, steps, chunk, flush=True)

@@ -5,7 +5,11 @@
     if the call had not been made;
   * non-finite arithmetic (a finite force far beyond any physical value)
     makes vanse_diagnostics return EUNSTABLE, and every later vanse_step and
-    batch step refuses (sticky);
+    batch step refuses (sticky); in the 16-bit fixed-point mode so does a
+    state outside its range;
+  * the 16-bit codes are relative to the mean initial M0 (a dense state
+    stays in range), and vanse_init refuses a rho0 whose mean is not
+    positive;
   * a member whose phi or force changes after the batch was built is stepped
     with the new parameters (bitwise equal to the same changes made alone).
 """
@@ -88,9 +92,12 @@ def test_rejected_force_field_leaves_the_solver_unchanged():
     t.close()
 
 
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FX16_SHIFTED])
 @pytest.mark.parametrize("fused", [False, True])
-def test_non_finite_arithmetic_makes_the_solver_unstable(fused):
-    s = _solver()
+def test_non_finite_arithmetic_makes_the_solver_unstable(fused, dtype):
+    """FX16 stores no NaN: the overflowing values saturate at the bound of
+    its range, which reads back as NaN."""
+    s = _solver(dtype)
     if fused:
         s.set_fused(1, 4)
     s.step(4)
@@ -110,7 +117,7 @@ def test_non_finite_arithmetic_makes_the_solver_unstable(fused):
         s.diagnostics()
     assert e.value.code == vanse.EUNSTABLE
     # a batch refuses a member that is unstable
-    ok = _solver(seed=4)
+    ok = _solver(dtype, seed=4)
     b = vanse.Batch([ok, s])
     with pytest.raises(vanse.VanseError) as e:
         b.step(2)
@@ -123,6 +130,89 @@ def test_non_finite_arithmetic_makes_the_solver_unstable(fused):
     assert np.isfinite(s.diagnostics()[0])
     ok.close()
     s.close()
+
+
+def _rho0(value, dims=DIMS):
+    return torch.full((int(np.prod(dims)),), value, dtype=torch.float64, device="cuda")
+
+
+def test_fx16_unit_keeps_a_dense_state_in_range():
+    """rho0 = 2 with phi in [0.5, 1] on a small grid (steep phi): M0 spans
+    [1, 2] and the populations reach 2.8 w_i.  In units of the mean initial
+    M0 (c ~ 1.5) the code h = f/(c w) - 1 stays within (-1, 1) over the run
+    (checked on the FP64 populations); in units of 1 it would leave it and
+    saturate.  The FX16 run stays finite and close to FP64 (2^-16 c w
+    rounding per step)."""
+    pert = torch.from_numpy(W.fourier_eps(DIMS, seed=3)).cuda()
+    u0 = torch.from_numpy(np.ascontiguousarray(W.taylor_green(DIMS, 0.01))).cuda()
+    c = float((2.0 * (0.75 + pert)).mean())
+    w = np.array(vanse.lattice_info(vanse.D3Q19)[2])[:, None]
+    out = []
+    for dt in (vanse.FP64, vanse.FX16_SHIFTED):
+        s = vanse.Solver("D3Q19", DIMS, 0.7, dt)
+        s.set_porosity(0.75, pert, 30.0)
+        s.init(_rho0(2.0), u0)
+        f0 = s.populations().cpu().numpy()
+        hmax = np.abs(f0 / (c * w) - 1.0).max()
+        h1 = np.abs(f0 / w - 1.0).max()
+        for _ in range(4):
+            s.step(10)
+            f = s.populations().cpu().numpy()
+            hmax = max(hmax, np.abs(f / (c * w) - 1.0).max())
+            h1 = max(h1, np.abs(f / w - 1.0).max())
+        if dt == vanse.FP64:
+            print("FP64 rho0 2: max |f/(c w) - 1|", hmax, "max |f/w - 1|", h1, flush=True)
+            assert hmax < 0.95 and h1 > 1.0
+        m = s.diagnostics()[0]
+        out.append((f0, m, [t.cpu().numpy() for t in s.moments()]))
+        s.close()
+    (f64, m64, (r64, p64, u64)), (f16, m16, (r, p, u)) = out
+    # initial populations: each within half a step of the code, c w 2^-16
+    # (plus the FP32 rounding of f/(c w) - 1 before it is coded)
+    assert np.all(np.abs(f16 - f64) <= c * w * (2.0 ** -16 + 1e-7))
+    er, eu = np.abs(r - r64).max() / np.abs(r64).max(), np.abs(u - u64).max() / np.abs(u64).max()
+    print("FX16 rho0 2: mass", (m16 - m64) / m64, "rho", er, "u", eu, flush=True)
+    assert abs(m16 - m64) <= 1e-6 * m64
+    assert er <= 1e-4 and eu <= 5e-4
+
+
+def test_fx16_state_outside_its_range_is_unstable_and_init_validates_the_centre():
+    n = int(np.prod(DIMS))
+    s = _solver(vanse.FX16_SHIFTED)
+    s.step(3)
+    # a cell 5 times denser than the rest: f/(c w) - 1 ~ 4 there, beyond +-1
+    rho0 = _rho0(1.0)
+    rho0[777] = 5.0
+    s.init(rho0)
+    f = s.populations().cpu().numpy()
+    assert np.all(np.isnan(f[:, 777])) and np.all(np.isfinite(np.delete(f, 777, axis=1)))
+    with pytest.raises(vanse.VanseError) as e:
+        s.diagnostics()
+    assert e.value.code == vanse.EUNSTABLE
+    with pytest.raises(vanse.VanseError) as e:
+        s.step(1)
+    assert e.value.code == vanse.EUNSTABLE
+    s.init()
+    s.step(2)
+    assert np.isfinite(s.diagnostics()[0])
+    # a rho0 whose mean is not finite and positive is refused before
+    # anything changes: the run continues as if the call had not been made
+    ref = _solver(vanse.FX16_SHIFTED)
+    ref.step(7)
+    want = ref.populations().cpu().numpy()
+    ref.close()
+    t = _solver(vanse.FX16_SHIFTED)
+    t.step(3)
+    for bad in (float("nan"), 0.0, -1.0):
+        with pytest.raises(vanse.VanseError) as e:
+            t.init(_rho0(bad))
+        assert e.value.code == vanse.EINVAL
+    assert t.time == 3
+    t.step(4)
+    assert np.array_equal(t.populations().cpu().numpy(), want)
+    t.close()
+    s.close()
+    assert n > 777
 
 
 @pytest.mark.parametrize("flags", [0, vanse.TUNE_TWO_STEP])

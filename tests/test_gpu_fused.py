@@ -94,7 +94,8 @@ SHAPES = [("D3Q19", (64, 8, 6), 1, 4), ("D3Q19", (64, 8, 6), 2, 32), ("D3Q19", (
           ("D3Q19", (130, 3, 2), 2, 2), ("D3Q27", (40, 6, 5), 4, 3), ("D3Q27", (17, 3, 2), 2, 1)]
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED,
+                                   vanse.FX16_SHIFTED])
 @pytest.mark.parametrize("lat,dims,rows,planes", SHAPES)
 def test_two_step_equals_single_steps_bitwise(lat, dims, rows, planes, dtype):
     print("case", lat, dims, rows, planes, dtype, flush=True)

@@ -86,7 +86,8 @@ def test_ablation_without_cell_integral_vs_oracle(lat, dims):
     _compare(lat, dims, 17, _case(lat, dims, 4, quad=vanse.QUAD_NONE))
 
 
-@pytest.mark.parametrize("dtype,tol", [(vanse.FP32_SHIFTED, 1e-5), (vanse.FP16_SHIFTED, 2e-2)])
+@pytest.mark.parametrize("dtype,tol", [(vanse.FP32_SHIFTED, 1e-5), (vanse.FP16_SHIFTED, 5e-3),
+                                       (vanse.FX16_SHIFTED, 2e-3)])
 def test_d3q27_reduced_storage_close_to_fp64(dtype, tol):
     dims = (24, 20, 16)
     from paper_2208_09267_amd import workloads as W
@@ -101,6 +102,9 @@ def test_d3q27_reduced_storage_close_to_fp64(dtype, tol):
         out.append([t.cpu().numpy() for t in s.moments()])
         s.close()
     (r64, p64, u64), (r, p, u) = out
+    print("D3Q27", dtype, "u", np.abs(u - u64).max() / np.abs(u64).max(), "p mean-free",
+          np.abs((p - p.mean()) - (p64 - p64.mean())).max() / np.abs(p64 - p64.mean()).max(),
+          flush=True)
     assert np.abs(u - u64).max() <= tol * np.abs(u64).max()
     assert np.abs((p - p.mean()) - (p64 - p64.mean())).max() <= tol * np.abs(p64 - p64.mean()).max()
 

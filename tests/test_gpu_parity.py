@@ -216,7 +216,8 @@ def test_device_side_validation_and_state_errors():
     s.close()
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED,
+                                   vanse.FX16_SHIFTED])
 def test_every_launch_shape_is_bitwise_identical(dtype):
     dims = (128, 6, 5)  # ROW tiling for blocks up to 128, FLAT above and with VANSE_TUNE_FLAT
     pert = W.fourier_eps(dims, seed=9)
@@ -237,7 +238,8 @@ def test_every_launch_shape_is_bitwise_identical(dtype):
             assert np.array_equal(f, ref), (block, flags)
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED,
+                                   vanse.FX16_SHIFTED])
 def test_every_tile_is_bitwise_identical(dtype):
     dims = (128, 8, 6)
     pert = W.fourier_eps(dims, seed=10)
@@ -282,13 +284,15 @@ def test_autotune_is_bitwise_neutral_and_counts_its_steps():
 # (storage, two-step rows, planes, tolerances on rho, p, u and on p against
 # the stricter scale |p - mean p|).  FP64: the 1e-11 bar.  The reduced
 # modes: about twice their recorded full-field errors against FP64 after
-# 2000 steps (FP32 shifted: 1.2e-6 / 3.9e-7 / 9.9e-7 absolute, i.e. 1.2e-6 /
-# 1.2e-6 / 4.7e-5 relative to the norms and 1.3e-4 of the pressure
-# deviation scale 0.0019; FP16 shifted: 7.1e-4 / 2.4e-4 / 3.9e-4 absolute,
-# i.e. 7e-4 / 7e-4 / 2.3e-2 relative and 0.13 of the deviation scale).
+# 2000 steps (absolute rho / p / u, then relative to the norms 1.01 / 0.337 /
+# 0.0212 and to the pressure deviation scale 0.0019):
+#   FP32 shifted  1.2e-6 / 3.9e-7 / 9.9e-7: 1.2e-6 / 1.2e-6 / 4.7e-5, 1.3e-4
+#   FP16 shifted  3.4e-4 / 1.1e-4 / 1.7e-4: 3.4e-4 / 3.4e-4 / 8.2e-3, 0.059
+#   FX16 shifted  3.8e-5 / 1.3e-5 / 2.2e-5: 3.7e-5 / 3.7e-5 / 1.05e-3, 6.6e-3
 BENCH_256 = [(vanse.FP64, 2, 128, (1e-11, 1e-11, 1e-11, 1e-9)),
              (vanse.FP32_SHIFTED, 4, 64, (3e-6, 3e-6, 1e-4, 3e-4)),
-             (vanse.FP16_SHIFTED, 4, 64, (1.5e-3, 1.5e-3, 5e-2, 0.3))]
+             (vanse.FP16_SHIFTED, 4, 64, (7e-4, 7e-4, 1.6e-2, 0.12)),
+             (vanse.FX16_SHIFTED, 4, 64, (8e-5, 8e-5, 2.1e-3, 1.3e-2))]
 
 
 @pytest.mark.parametrize("dtype,rows,planes,tol", BENCH_256)
@@ -301,7 +305,7 @@ def test_d3q19_256_full_run_in_bench_launch_vs_oracle_samples(dtype, rows, plane
     import bench
 
     name = {vanse.FP64: "fp64", vanse.FP32_SHIFTED: "fp32_shifted",
-            vanse.FP16_SHIFTED: "fp16_shifted"}[dtype]
+            vanse.FP16_SHIFTED: "fp16_shifted", vanse.FX16_SHIFTED: "fx16_shifted"}[dtype]
     assert bench.FIXED_LAUNCH[name][3:] == (rows, planes)
     label = bench.kernel_name(name, rows)
     assert label == "fused2_kernel<D3Q19, %s, rows %d>" % (bench.MODE_NAME[name], rows)

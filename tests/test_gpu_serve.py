@@ -75,7 +75,8 @@ def test_over_budget_request_is_refused():
     assert res[1].error is None
 
 
-@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED])
+@pytest.mark.parametrize("dtype", [vanse.FP64, vanse.FP32_SHIFTED, vanse.FP16_SHIFTED,
+                                   vanse.FX16_SHIFTED])
 def test_state_bytes_matches_library(dtype):
     for dims in [(8, 8, 8), (33, 17, 5), (1, 1, 1)]:
         s = vanse.Solver("D3Q19", dims, 0.7, dtype)

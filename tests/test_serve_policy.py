@@ -44,7 +44,8 @@ def test_steps_until_host():
 
 
 @pytest.mark.parametrize("dtype,elem,pert", [(vanse.FP64, 8, 8), (vanse.FP32_SHIFTED, 4, 4),
-                                             (vanse.FP16_SHIFTED, 2, 4)])
+                                             (vanse.FP16_SHIFTED, 2, 4),
+                                             (vanse.FX16_SHIFTED, 2, 4)])
 def test_state_bytes_formula(dtype, elem, pert):
     n = 33 * 17 * 5
     stride = (n + 127) // 128 * 128
