@@ -28,8 +28,8 @@ NCELLS_256 = 256 ** 3
 COPY_BYTES = 1 << 30            # bytes copied by bench.py's copy_probe
 MODES = {0: "fp64", 1: "fp32_shifted", 2: "fp16_shifted", 3: "fx16_shifted"}
 MODE_LABEL = {0: "FP64", 1: "FP32_SHIFTED", 2: "FP16_SHIFTED", 3: "FX16_SHIFTED"}
-ELEM = {0: 8, 1: 4, 2: 2}
-PERT = {0: 8, 1: 4, 2: 4}
+ELEM = {0: 8, 1: 4, 2: 2, 3: 2}
+PERT = {0: 8, 1: 4, 2: 4, 3: 4}
 LATTICE_Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
 
 
