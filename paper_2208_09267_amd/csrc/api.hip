@@ -51,6 +51,7 @@ struct vanse_batch {
     bool fused_ok = false;              // every member has a general tile
     int uni_nx = 0, uni_rows = 0;       // the members' common compile-time tile (0: general tiles)
     bool xt = false;                    // general tiles with x-split members
+    int gen_threads = 512;              // block size of full-row general tiles
     unsigned nblocks2 = 0;
     size_t lds2 = 0;                    // LDS bytes per block of the two-step grid
     vanse::BatchMember *d_members2 = nullptr;
@@ -946,9 +947,26 @@ int batch_layout2(vanse_batch *b)
         }
         xt = ok_xt && split;
     }
+    // Full-row general tiles in 768-thread blocks (one halo cell per thread,
+    // 3 waves per SIMD) when every member is at most 96 cells wide, where
+    // they hold more rows than the 512-thread tile (32: 22 rows against 16,
+    // 96: 6 against 5): the 64-solve batch of edges 32-96 ran at 55.3 GLUPS
+    // against 53.4.  Wider members keep 512 threads: at equal rows the
+    // 768-thread tile leaves more threads idle (the served stream, edges up to
+    // 192, ran at 38.8 GLUPS against 41.4 with 768 threads everywhere).
+    int gen_threads = vanse::kFusedThreads;
+    if (uni_rows == 0 && !xt && b->lattice == VANSE_D3Q19 && b->mode != vanse::MODE_F64) {
+        bool narrow = true;
+        for (int k = 0; k < b->count && narrow; ++k) {
+            const Solver &s = b->members[k]->s;
+            narrow = s.geo.nx <= 96 &&
+                     vanse::batch_fused_rows(s, vanse::kGenThreads768) >= vanse::batch_fused_rows(s);
+        }
+        if (narrow) gen_threads = vanse::kGenThreads768;
+    }
     auto tile_rows = [&](int k) {
         const Solver &s = b->members[k]->s;
-        return uni_rows ? uni_rows : (xt ? xt_rows[k] : vanse::batch_fused_rows(s));
+        return uni_rows ? uni_rows : (xt ? xt_rows[k] : vanse::batch_fused_rows(s, gen_threads));
     };
     auto tile_cols = [&](int k) {
         const Solver &s = b->members[k]->s;
@@ -1050,6 +1068,7 @@ int batch_layout2(vanse_batch *b)
     b->uni_nx = uni_nx;
     b->uni_rows = uni_rows;
     b->xt = xt;
+    b->gen_threads = gen_threads;
     b->fused_ok = true;
     return VANSE_OK;
 }
@@ -1141,7 +1160,7 @@ hipError_t batch_launch(vanse_batch *b, int j, hipStream_t st)
 hipError_t batch_launch2(vanse_batch *b, int j, int swap, hipStream_t st)
 {
     const double *mtab = reinterpret_cast<const double *>(b->d_tab);
-    return vanse::launch_batch_fused(b->lattice, b->mode, b->uni_nx, b->uni_rows, b->xt,
+    return vanse::launch_batch_fused(b->lattice, b->mode, b->uni_nx, b->uni_rows, b->xt, b->gen_threads,
                                      b->nblocks2, b->lds2, b->d_members2, b->d_owner2, mtab, j,
                                      b->count, swap, st);
 }

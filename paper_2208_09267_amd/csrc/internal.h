@@ -128,6 +128,11 @@ StepArgs step_args(const Solver &s, int64_t n);
 // Kernel launchers (kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_step(const Solver &s, const StepArgs &a, int parity);
 constexpr int kFusedThreads = 512;    // threads per block of the two-step launch
+// general tiles of batches whose members are all narrow (nx <= 96, D3Q19,
+// reduced storage): blocks of 768 threads, one interior and one halo cell
+// per thread (145 VGPRs: 3 waves per SIMD, where the 512-thread tile with
+// two halo cells per thread holds 193 VGPRs and 2 waves)
+constexpr int kGenThreads768 = 768;
 constexpr int kFusedMaxLds = 160 * 1024;
 // Tile shapes of the two-step launch compiled into the library: ipt interior
 // and hpt halo-plane cells per thread, kept to the combinations whose
@@ -183,8 +188,9 @@ hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, u
                              const BatchMember *members, const unsigned *owner,
                              const double *mtab, const long long *t0, int j, int count,
                              hipStream_t st);
-// Rows of a solve's general tile in the batched two-step launch (0: none).
-int batch_fused_rows(const Solver &s);
+// Rows of a solve's general tile in the batched two-step launch with blocks
+// of `threads` (kFusedThreads or kGenThreads768) threads (0: none).
+int batch_fused_rows(const Solver &s, int threads = kFusedThreads);
 // The general tile of a D3Q19 solve in a batched two-step launch with x-split
 // members: full rows (*cols = nx) where they fit a block, else *cols >= 48
 // interior columns of a split of the x-rows and *rows rows, chosen to load
@@ -200,7 +206,9 @@ int batch_uniform_rows(int lattice, int mode, int nx, int ny);
 // uni_nx, uni_rows: the members' common compile-time tile, or 0, 0 for
 // general tiles (each member's own rows).
 // xt: general tiles with x-split members (batch_xt_tile), D3Q19 only.
-hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, bool xt,
+// gen_threads: block size of full-row general tiles (kFusedThreads, or
+// kGenThreads768 for D3Q19 in the reduced modes).
+hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, bool xt, int gen_threads,
                               unsigned nblocks, size_t lds, const BatchMember *members,
                               const unsigned *owner, const double *mtab, int j, int count,
                               int swap, hipStream_t st);

@@ -1375,12 +1375,15 @@ hipError_t launch_fused(const Solver &s, const StepArgs &a)
     return rc;
 }
 
-int batch_fused_rows(const Solver &s)
+int batch_fused_rows(const Solver &s, int threads)
 {
     if (s.d != 3 || (long long)s.geo.ncells * 8 >= (1ll << 32)) return 0;
     const int nx = s.geo.nx;
     int rows;
-    if (s.mode == MODE_F64) {
+    if (threads == kGenThreads768) {
+        if (s.lattice != 1 || s.mode == MODE_F64) return 0;
+        rows = kGenThreads768 / nx - 2;                 // 1 interior, 1 halo cell per thread
+    } else if (s.mode == MODE_F64) {
         if (s.lattice != 1) return 0;
         rows = 512 / nx - 2;                            // 1 interior, 1 halo cell per thread
     } else {
@@ -1448,7 +1451,7 @@ bool batch_xt_tile(const Solver &s, int *cols, int *rows)
     return true;
 }
 
-hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, bool xt,
+hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, bool xt, int gen_threads,
                               unsigned nblocks, size_t lds, const BatchMember *members,
                               const unsigned *owner, const double *mtab, int j, int count,
                               int swap, hipStream_t st)
@@ -1476,6 +1479,7 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, b
             GEN ? fused_compiled_gen(LAT, M, I, H) : fused_compiled(LAT, M, I, H, NXC);
         if constexpr (compiled) {
             if (launched || NXC != uni_nx || TYC != uni_rows || XT != xt) return;
+            if (GEN && !XT && NTC != gen_threads) return;
             auto *fn = &batch_fused2_kernel<L, M, KI, KH, NXC, TYC, GEN, NTC, XT>;
             static std::atomic<unsigned long long> raised{0};
             int dev = 0;
@@ -1511,6 +1515,12 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, b
             using X = std::true_type;
             if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{}, N512{}, F{});
             else go(lat, m, C1{}, C2{}, C0{}, C0{}, N512{}, F{});
+            if constexpr (std::is_same<L, D3Q19>::value && M != MODE_F64) {
+                // general tiles of batches of narrow members: 768-thread
+                // blocks, one interior and one halo cell per thread
+                using N768 = std::integral_constant<int, kGenThreads768>;
+                go(lat, m, C1{}, C1{}, C0{}, C0{}, N768{}, F{});
+            }
             if constexpr (std::is_same<L, D3Q19>::value) {
                 // general tiles with x-split members
                 if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{}, N512{}, X{});

@@ -291,6 +291,21 @@ XT_CASES = [(192, 20, 9, 16, 4, 32), (192, 11, 7, 5, 3, 96), (130, 9, 6, 6, 5, 4
             (360, 7, 5, 7, 5, 72)]
 
 
+# general tiles of batches of narrow members: 768-thread blocks, one
+# interior and one halo cell per thread, rows = 768 / nx - 2 (at most ny):
+# (nx, ny, nz, rows, planes)
+GEN768_CASES = [(32, 32, 5, 22, 2), (48, 48, 4, 14, 3), (64, 64, 3, 10, 3), (96, 96, 3, 6, 2),
+                (17, 13, 11, 13, 6), (80, 80, 3, 7, 2), (67, 13, 4, 9, 4), (5, 64, 7, 64, 3),
+                (33, 40, 3, 21, 2)]
+
+
+@pytest.mark.parametrize("case", GEN768_CASES)
+def test_two_step_general_tile_indexing_768_threads(case):
+    nx, ny, nz, rows, planes = case
+    assert rows == min(768 // nx - 2, ny)
+    assert check(nx, ny, nz, rows, planes, D3Q19, full=True, NT=768)
+
+
 @pytest.mark.parametrize("lat", ["D3Q19"])
 @pytest.mark.parametrize("case", XT_CASES)
 def test_two_step_x_split_tile_indexing(case, lat):
