@@ -81,6 +81,32 @@ def test_d2q9_64_full_run_vs_oracle():
     assert np.abs(p - p_o).max() / np.abs(p_o - p_o.mean()).max() <= 1e-9
 
 
+# (storage, tolerances on rho relative to its norm, u relative to its norm,
+# p against the deviation scale |p - mean p|): about twice the measured
+# errors (FP32 3.0e-6 / 3.9e-5 / 1.3e-4, FP16 2.4e-4 / 4.1e-2 / 0.15, FX16
+# 6.4e-5 / 9.4e-3 / 5.2e-2; this workload's pressure deviations are small,
+# 0.15 of phi's swing over a smooth field)
+D2Q9_REDUCED = [(vanse.FP32_SHIFTED, (1e-5, 1e-4, 3e-4)), (vanse.FP16_SHIFTED, (5e-4, 0.1, 0.3)),
+                (vanse.FX16_SHIFTED, (1.5e-4, 0.02, 0.1))]
+
+
+@pytest.mark.parametrize("dtype,tol", D2Q9_REDUCED)
+def test_d2q9_64_reduced_storage_vs_oracle(dtype, tol):
+    """The D2Q9 64^2 workload (1000 steps, body force, modulated phi) in the
+    reduced storage modes against the oracle's FP64 fields."""
+    w = W.d2q9_64()
+    pert = w.eps_pert()
+    s, rho, p, u = gpu_run(w.lattice, w.dims, w.tau, w.eps_mean, pert, w.period, w.steps,
+                           force=w.force, dtype=dtype)
+    s.close()
+    _, rho_o, p_o, u_o = oracle_run(w.lattice, w.dims, w.tau, w.eps_mean, pert, w.period,
+                                    w.steps, force=w.force)
+    er, eu = rel_linf(rho, rho_o), rel_linf(u, u_o)
+    ep = np.abs((p - p.mean()) - (p_o - p_o.mean())).max() / np.abs(p_o - p_o.mean()).max()
+    print(dtype, "rel Linf rho %.3e u %.3e p mean-free %.3e" % (er, eu, ep), flush=True)
+    assert er <= tol[0] and eu <= tol[1] and ep <= tol[2]
+
+
 def test_d3q19_ragged_grid_vs_oracle():
     dims = (40, 36, 33)
     pert = W.fourier_eps(dims, seed=7)
