@@ -223,20 +223,25 @@ int vanse_batch_set_stream(vanse_batch_t b, void *stream);
  *       most 32, 16 or 8 when a host-side estimate of the launch finds the
  *       batch too small to fill the GPU with 64); otherwise each
  *       member gets general tiles (any size) of as many x-rows as fit 512
- *       interior and 1024 (FP64: 512) halo-plane cells per block, and its nz
- *       is split into equal segments of at most 32 planes (at most 24, 16,
- *       12 or 8 when a host-side estimate of the launch finds the batch too
- *       small to fill the GPU with 32; vanse_batch_two_step_layout reports
- *       the result).  On D3Q19, when a member's full rows do not fit a
- *       block (nx > 340; FP64 nx > 170), general tiles split the x-rows of
- *       wide members into segments of at least 48 columns with a halo
- *       column on each side (vanse_batch_two_step_tiles reports them).  Every member gets a second population array
- *       (allocated here, kept by the member's solver: its population memory
- *       doubles).  Used for every group of 4 steps of a chunk while all
- *       members sit at even time levels (two launches, so each member ends
- *       the group in its first array); other steps, and batches whose members
- *       do not fit such a tile (nx > 340; FP64 nx > 170; D3Q27 in FP64),
- *       use the single-step batched launch.
+ *       interior and 1024 (FP64: 512) halo-plane cells per 512-thread
+ *       block, and its nz is split into equal segments of at most 32 planes
+ *       (at most 24, 16, 12 or 8 when a host-side estimate of the launch
+ *       finds the batch too small to fill the GPU with 32;
+ *       vanse_batch_two_step_layout reports the result).  A D3Q19 batch in
+ *       reduced storage whose members are all at most 96 cells wide takes
+ *       768-thread blocks instead, with as many x-rows as fit 768
+ *       halo-plane cells (more rows per tile).  On D3Q19, when a member's
+ *       full rows do not fit a block (nx > 340; FP64 nx > 170), general
+ *       tiles split the x-rows of wide members into segments of at least
+ *       48 columns with a halo column on each side
+ *       (vanse_batch_two_step_tiles reports them).  Every member gets a
+ *       second population array (allocated here, kept by the member's
+ *       solver: its population memory doubles).  Used for every group of 4
+ *       steps of a chunk while all members sit at even time levels (two
+ *       launches, so each member ends the group in its first array); other
+ *       steps, and batches with a member that has no such tile (D3Q27 in
+ *       FP64, or wider than 340 on D3Q27), use the single-step batched
+ *       launch.
  * Results do not depend on any of these.  Errors: EINVAL, ENOMEM. */
 int vanse_batch_set_tuning(vanse_batch_t b, int block, int flags, int chunk);
 
