@@ -929,20 +929,18 @@ int batch_layout2(vanse_batch *b)
     }
     if (uni_rows == 0) uni_nx = 0;
     // General tiles: full x-rows; on D3Q19, x-split tiles when a member's
-    // full rows do not fit a block (FP64 wider than 170 cells, FP32/FP16
-    // wider than 340), so that such batches still take the two-step launch.
-    // Where full rows fit they are kept even if a split loads fewer halo
-    // cells: measured on 192^3 and 250^3 solves and the served stream,
-    // full-row tiles of 2-3 rows beat every split of 32-125 columns (FP32
-    // 192^3: 46.7 GLUPS against 33-40), although the splits load fewer halo
-    // cells.
+    // full rows do not fit a block (FP64 wider than 170 cells, reduced
+    // storage wider than 341), so that such batches still take the two-step
+    // launch.  Where full rows fit they are kept even if a split loads fewer
+    // halo cells (measured on 192^3 and 250^3 solves and the served stream).
     std::vector<int> xt_cols(b->count, 0), xt_rows(b->count, 0);
     bool xt = false;
     if (uni_rows == 0 && b->lattice == VANSE_D3Q19) {
+        const int split_above = b->mode == vanse::MODE_F64 ? 170 : 341;
         bool ok_xt = true, split = false;
         for (int k = 0; k < b->count && ok_xt; ++k) {
             const Solver &s = b->members[k]->s;
-            if (!vanse::batch_xt_tile(s, &xt_cols[k], &xt_rows[k])) ok_xt = false;
+            if (!vanse::batch_xt_tile(s, split_above, &xt_cols[k], &xt_rows[k])) ok_xt = false;
             else split = split || xt_cols[k] < s.geo.nx;
         }
         xt = ok_xt && split;

@@ -191,11 +191,11 @@ hipError_t launch_batch_step(int lattice, int mode, bool nt, unsigned nblocks, u
 // Rows of a solve's general tile in the batched two-step launch with blocks
 // of `threads` (kFusedThreads or kGenThreads768) threads (0: none).
 int batch_fused_rows(const Solver &s, int threads = kFusedThreads);
-// The general tile of a D3Q19 solve in a batched two-step launch with x-split
-// members: full rows (*cols = nx) where they fit a block, else *cols >= 48
-// interior columns of a split of the x-rows and *rows rows, chosen to load
-// the fewest halo cells per interior cell; false if the solve has neither.
-bool batch_xt_tile(const Solver &s, int *cols, int *rows);
+// The tile of a D3Q19 solve in a batched two-step launch with x-split
+// members: full rows (*cols = nx) when nx <= split_above or nx <= 62 (false
+// if they do not fit), else segments of at most 62 columns, one wave per
+// row; *rows rows.
+bool batch_xt_tile(const Solver &s, int split_above, int *cols, int *rows);
 // LDS of one block of an x-split tile (cols < nx): slab and a ring of 5
 // perturbation planes of (rows + 4) x (cols + 4) values.
 size_t fused_lds_bytes_xt(int q, int mode, int cols, int rows);

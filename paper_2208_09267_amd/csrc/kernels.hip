@@ -586,9 +586,12 @@ __global__ void __launch_bounds__(256) batch_step_kernel(const BatchMember *__re
 // into segments of a.ftx columns (a shorter last one), numbered x-fastest;
 // such a tile adds a halo column on each side (its x-neighbours recompute
 // them, as its outer rows), and its phi ring spans the tile's columns plus
-// two on each side.  A member whose a.ftx covers its whole row (a.ftx >= nx)
-// keeps the full-row indexing of the general tile (no halo columns: x wraps
-// inside the row).  Needs nx >= 8 when a.ftx < nx.
+// two on each side.  Its rows of at most 64 cells (a.ftx + 2 <= 64) each
+// go to one wave, lane = column, so IPT and HPT count rows per wave: at most
+// IPT * NT/64 interior rows, and HPT * NT/64 rows with the two outer ones.
+// A member whose a.ftx covers its whole row (a.ftx >= nx) keeps
+// the full-row indexing of the general tile (no halo columns: x wraps inside
+// the row).  Needs nx >= 8 when a.ftx < nx.
 template <class L, int MODE, int IPT, int HPT, int NXC, int TYC, bool GEN, int NT, bool XT = false>
 __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
 {
@@ -604,8 +607,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
     constexpr int RING = 5;                 // pert planes p-2 .. p+2
     // pert values per thread and plane: exact for the compile-time tiles,
     // else a bound from the halo cells per thread ((rows + 4) / (rows + 2) <= 5/3)
-    // (x-split tiles: (rows + 4)(cols + 4) <= 2 (rows + 2)(cols + 2) whenever
-    // rows * cols >= 8, which the host ensures)
+    // (x-split tiles: (rows + 4)(cols + 4) <= (HPT NT/64 + 2) 66 <= 2 HPT NT)
     constexpr int PPT = (NXC > 0 && TYC > 0) ? ((TYC + 4) * NXC + NT - 1) / NT
                                              : (XT ? 2 * HPT : (5 * HPT + 2) / 3);
     extern __shared__ __align__(16) unsigned char fused_lds[];
@@ -672,6 +674,43 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
     // ring column c (x0 - 2 + c, wrapped); full rows: the column itself
     auto halo_x = [&](int hx) { return xs ? wrap(x0 - 1 + hx, nx) : hx; };
     auto ring_x = [&](int c) { return xs ? wrap(x0 - 2 + c, nx) : c; };
+    // Cells of the tile handled by a thread.  Full rows: tile cells numbered
+    // row by row, thread tid takes cell tid + pass * NT.  x-split tiles (HW <=
+    // 64): one wave per row segment, lane = column, wave w takes row w + pass
+    // * NW, so a wave's loads, LDS accesses and stores stay within one row
+    // segment; lanes past the segment (and rows past the tile, which only
+    // whole waves reach) repeat its last cell and are masked.
+    constexpr int NW = NT / 64;
+    const int lane = tid & 63, wv = tid >> 6;
+    // halo cell of pass h: row hr (0 .. TY+1), column hx (0 .. HW-1), valid
+    auto halo_cell = [&](int h, int &hr, int &hx, bool &valid) {
+        if (xs) {
+            const int r = wv + h * NW;
+            valid = lane < HW && r < TY + 2;
+            hr = min(r, TY + 1);
+            hx = min(lane, HW - 1);
+        } else {
+            const int idx = min(tid + h * NT, HC - 1);
+            valid = tid + h * NT < HC;
+            hr = hrow(idx);
+            hx = idx - hr * HW;
+        }
+    };
+    // interior cell of pass k: row r (0 .. TY-1), column cx (0 .. TX-1), and
+    // whether this thread owns it
+    auto interior_cell = [&](int k, int &r, int &cx, bool &owned) {
+        if (xs) {
+            const int rr = wv + k * NW;
+            owned = lane < TX && rr < TY;
+            r = min(rr, TY - 1);
+            cx = min(lane, TX - 1);
+        } else {
+            const int cell = min(tid + k * NT, NI - 1);
+            owned = tid + k * NT < NI;
+            r = irow(cell);
+            cx = cell - r * TX;
+        }
+    };
     // element offset -> byte offset (GEN: 32-bit, checked on the host)
     auto boff = [](int elem, unsigned size) { return (unsigned)elem * size; };
     // Ring slot s holds the pert rows of one plane at ring + s * PC; plane q
@@ -718,9 +757,10 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
     // natural-order populations of halo cell h (of the fty + 2 rows) of plane p
     auto load_cell = [&](T (&raw_h)[Q], int h, int p) {
         const int pz = zmod(p);
-        const int idx = min(tid + h * NT, HC - 1);
-        const int hr = hrow(idx);
-        const int x = halo_x(idx - hr * HW);
+        int hr, hx;
+        bool valid;
+        halo_cell(h, hr, hx, valid);
+        const int x = halo_x(hx);
         const int y = wrap(y0 + hr - 1, ny);
         if constexpr (GEN) {
             const unsigned o = boff(pz * nxy + y * nx + x, sizeof(T));
@@ -789,9 +829,15 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         store_pert(ph, sp2);
         static_for<0, HPT>([&](auto hc) {
             constexpr int h = decltype(hc)::value;
-            const int idx = min(tid + h * NT, HC - 1);
-            const int hr = hrow(idx);
-            const int hx = idx - hr * HW;   // halo column (full rows: x)
+            int hr, hx;   // halo row and column (full rows: hx = x)
+            bool valid = true;
+            if constexpr (XT) {
+                halo_cell(h, hr, hx, valid);
+            } else {
+                const int idx = min(tid + h * NT, HC - 1);
+                hr = hrow(idx);
+                hx = idx - hr * HW;
+            }
             const int x = halo_x(hx);
             R v[Q];
             static_for<0, Q>([&](auto ic) {
@@ -806,7 +852,11 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
             // every wave issues the same memory operations, and skips the
             // collision and the pushes
             constexpr bool FULL = !GEN && NXC > 0 && TYC > 0 && (h + 1) * NT <= (TYC + 2) * NXC;
-            if (FULL || (tid & ~63) + h * NT < HC) {
+            bool wave_on = (tid & ~63) + h * NT < HC;
+            if constexpr (XT) {
+                if (xs) wave_on = wv + h * NW < TY + 2;  // its row lies in the tile
+            }
+            if (FULL || wave_on) {
                 update(v, x, wrap(y0 + hr - 1, ny), hr + 1, xs ? hx + 1 : x, ring_m1, ring_0,
                        ring_p1, pz, R(a.m));
                 // destination rows hr - 1 + cy of the slab and columns x + cx
@@ -819,7 +869,7 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
                     constexpr int i = decltype(ic)::value;
                     const int r = hr - 1 + L::cy[i];
                     bool in = (unsigned)r < (unsigned)TY;  // wave-uniform unless GEN
-                    if constexpr (XT) in = in && (unsigned)Xd[L::cx[i] + 1] < (unsigned)TX;
+                    if constexpr (XT) in = in && valid && (unsigned)Xd[L::cx[i] + 1] < (unsigned)TX;
                     if (in)
                         slab[i * NI + Ro[L::cy[i] + 1] + Xd[L::cx[i] + 1]] = St::encode(v[i]);
                 });
@@ -833,15 +883,23 @@ __device__ __forceinline__ void fused2_tile(const StepArgs &a, unsigned b)
         const int z = max(p - 1, z0);
         static_for<0, IPT>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
-            const bool own = tid + k * NT < NI && p > z0;  // wave-uniform unless GEN
-            const int cell = min(tid + k * NT, NI - 1);
+            bool own;     // wave-uniform unless GEN
+            int cell, r, cx;   // slab cell, interior row and column (full rows: cx = x)
+            if constexpr (XT) {
+                interior_cell(k, r, cx, own);
+                own = own && p > z0;
+                cell = r * TX + cx;
+            } else {
+                own = tid + k * NT < NI && p > z0;
+                cell = min(tid + k * NT, NI - 1);
+                r = irow(cell);
+                cx = cell - r * TX;
+            }
             R t[Q];
             static_for<0, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
                 t[i] = St::decode(slab[i * NI + cell]);
             });
-            const int r = irow(cell);
-            const int cx = cell - r * TX;   // interior column (full rows: x)
             const int x = x0 + cx;
             const int y = y0 + r;
             R w[Q];
@@ -1411,43 +1469,32 @@ size_t fused_lds_bytes_xt(int q, int mode, int cols, int rows)
     return slab + ring;
 }
 
-// Full rows where they fit a block (measured faster than any split on FP32
-// 192^3 and 250^3 solves: 46.7 and 48.3 GLUPS against 33-45); otherwise the
-// split of the x-rows into k >= 2 segments of at least 48 columns with the
-// most interior cells per loaded halo-plane cell (on FP64 192^3 and 250^3,
-// 48-50 columns gave 22.1-24.2 GLUPS, 32 columns 20.6-22.3, 64 or more
-// 19.0-21.4).
-bool batch_xt_tile(const Solver &s, int *cols, int *rows)
+// Rows and columns of a D3Q19 solve's tile in a batched launch with x-split
+// members, whose kernel has one interior and one halo cell (FP64) or two and
+// two (reduced storage) per thread: full rows where they fit (*cols = nx,
+// as many rows as the cells per thread allow), unless split_above < nx;
+// otherwise the fewest segments of at most 62 columns (a halo column on each
+// side makes a row of at most 64: one wave per row) and as many rows as
+// 8 waves hold (FP64 6, reduced 14).
+bool batch_xt_tile(const Solver &s, int split_above, int *cols, int *rows)
 {
     if (s.lattice != 1 || s.d != 3 || (long long)s.geo.ncells * 8 >= (1ll << 32)) return false;
     const int nx = s.geo.nx, ny = s.geo.ny;
-    const int full = batch_fused_rows(s);
-    if (full > 0) {
+    const int per = s.mode == MODE_F64 ? 1 : 2;        // interior and halo cells per thread
+    const int full = std::min(per * kFusedThreads / nx - 2, ny);
+    if (nx <= split_above || nx <= 62) {
+        if (full < 1) return false;
         *cols = nx;
         *rows = full;
         return true;
     }
-    // a 512-thread block: one interior cell per thread, two halo cells (FP64:
-    // one), as the general full-row tile
-    const int ni_max = kFusedThreads, hc_max = s.mode == MODE_F64 ? kFusedThreads : 2 * kFusedThreads;
-    int best_c = 0, best_r = 0;
-    double best = 0.0;  // interior cells per loaded cell
-    for (int k = 2; k <= 16; ++k) {
-        const int c = (nx + k - 1) / k;
-        if (c < 48) break;
-        const int r = std::min(std::min(ni_max / c, hc_max / (c + 2) - 2), ny);
-        if (r < 1) continue;
-        if (fused_lds_bytes_xt(s.q, s.mode, c, r) > (size_t)kFusedMaxLds) continue;
-        const double eff = (double)c * r / ((double)(c + 2) * (r + 2));
-        if (eff > best) {
-            best = eff;
-            best_c = c;
-            best_r = r;
-        }
-    }
-    if (best_r == 0) return false;
-    *cols = best_c;
-    *rows = best_r;
+    const int k = (nx + 61) / 62;
+    const int c = (nx + k - 1) / k;
+    const int nw = kFusedThreads / 64;
+    const int r = std::min(per * nw - 2, ny);
+    if (fused_lds_bytes_xt(s.q, s.mode, c, r) > (size_t)kFusedMaxLds) return false;
+    *cols = c;
+    *rows = r;
     return true;
 }
 
@@ -1524,7 +1571,7 @@ hipError_t launch_batch_fused(int lattice, int mode, int uni_nx, int uni_rows, b
             if constexpr (std::is_same<L, D3Q19>::value) {
                 // general tiles with x-split members
                 if constexpr (M == MODE_F64) go(lat, m, C1{}, C1{}, C0{}, C0{}, N512{}, X{});
-                else go(lat, m, C1{}, C2{}, C0{}, C0{}, N512{}, X{});
+                else go(lat, m, C2{}, C2{}, C0{}, C0{}, N512{}, X{});
                 go(lat, m, C2{}, C3{}, C256{}, C4{}, N1024{}, F{});
                 go(lat, m, C1{}, C2{}, C256{}, C2{}, N512{}, F{});
                 go(lat, m, C1{}, C2{}, C128{}, C4{}, N512{}, F{});

@@ -54,8 +54,12 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
     XT = TXMAX is not None
     xs = XT and TXMAX < nx
     compile_time = (nx, TY) in tiles and ny % TY == 0 and not XT
+    NW = NT // 64
     if xs:
-        IPT, HPT = -(-TXMAX * TY // NT), -(-(TXMAX + 2) * (TY + 2) // NT)
+        # one wave per tile row of at most 64 cells: cells per thread count
+        # rows per wave
+        assert TXMAX + 2 <= 64
+        IPT, HPT = -(-TY // NW), -(-(TY + 2) // NW)
     if compile_time:
         PPT = -(-(TY + 4) * nx // NT)
     elif XT:
@@ -66,6 +70,7 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
     fnyb = -(-ny // TY) * fnxb
     nzb = -(-nz // SZ)
     tid = np.arange(NT)
+    lane, wv = tid & 63, tid >> 6
     written = np.zeros((Q, ncells), np.int32)
 
     def wrap(v, n):
@@ -94,7 +99,31 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
 
         def ring_x(c):
             return wrap(x0 - 2 + c, nx) if xs else c
-        assert PC <= PPT * NT and NI <= IPT * NT and HC <= HPT * NT
+
+        def halo_map(h):
+            """(row, column, real) of each thread's halo cell in pass h."""
+            if xs:
+                r = wv + h * NW
+                return (np.minimum(r, TY + 1), np.minimum(lane, HW - 1),
+                        (lane < HW) & (r < TY + 2))
+            idx = np.minimum(tid + h * NT, HC - 1)
+            hr = idx // HW
+            return hr, idx - hr * HW, tid + h * NT < HC
+
+        def interior_map(k):
+            """(row, column, owned) of each thread's interior cell in pass k."""
+            if xs:
+                rr = wv + k * NW
+                return (np.minimum(rr, TY - 1), np.minimum(lane, TX - 1),
+                        (lane < TX) & (rr < TY))
+            cell = np.minimum(tid + k * NT, NI - 1)
+            r = cell // TX
+            return r, cell - r * TX, tid + k * NT < NI
+        assert PC <= PPT * NT
+        if xs:
+            assert HW <= 64 and TY + 2 <= HPT * NW and TY <= IPT * NW
+        else:
+            assert NI <= IPT * NT and HC <= HPT * NT
         z0 = bz * SZ
         z1 = min(z0 + SZ, nz)
         ring = {}          # slot -> (plane, iteration written; -99 prologue)
@@ -135,9 +164,8 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
         def load_plane(p):
             pz = zmod(p)
             for h in range(HPT):
-                idx = np.minimum(tid + h * NT, HC - 1)
-                hr = idx // HW
-                x = halo_x(idx - hr * HW)
+                hr, hx, _ = halo_map(h)
+                x = halo_x(hx)
                 y = wrap(y0 + hr - 1, ny)
                 for i in range(Q):
                     a = i * S + pz * nxy + y * nx + x
@@ -162,9 +190,7 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
             assert pending_pert == p + 2
             # halo phase
             for h in range(HPT):
-                idx = np.minimum(tid + h * NT, HC - 1)
-                hr = idx // HW
-                hx = idx - hr * HW
+                hr, hx, real = halo_map(h)
                 x = halo_x(hx)
                 c = hx + 1 if xs else x
                 cm = c - 1 if xs else np.where(c == 0, nx, c) - 1
@@ -175,19 +201,24 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
                                          (p, r + 1, c, x), (p, r - 1, c, x), (p + 1, r, c, x),
                                          (p - 1, r, c, x)):
                     ring_read(qq, rr, cc, p, "halo", gx)
-                real = tid + h * NT < HC  # lanes past the last halo cell repeat it
-                # the halo-wave skip: a wave collides and pushes only if its
-                # first lane is a real halo cell, or the compile-time constant
-                # FULL says every lane of this halo slot is real
+                # lanes past the last halo cell (x-split tiles: past the row
+                # segment, or rows past the tile) repeat a real cell.  The
+                # halo-wave skip: a wave collides and pushes only if its first
+                # lane is a real halo cell (x-split tiles: its row lies in the
+                # tile), or the compile-time constant FULL says every lane of
+                # this halo slot is real
                 FULL = compile_time and (h + 1) * NT <= (TYMAX + 2) * nx
-                computing = FULL | ((tid & ~63) + h * NT < HC)
+                if xs:
+                    computing = wv + h * NW < TY + 2
+                else:
+                    computing = FULL | ((tid & ~63) + h * NT < HC)
                 if FULL:
                     assert np.all(real), "FULL with a lane past the tile"
                 assert np.all(computing[real]), "a real halo cell in a skipped wave"
                 # a computing lane past the tile repeats the last halo cell, which
                 # its own (real) lane computes from the same inputs in this phase
                 rep = computing & ~real
-                if rep.any():
+                if rep.any() and not XT:
                     assert computing_last, "the repeated cell is not computed"
                 for i, (cx, cy, cz) in enumerate(lat):
                     rd = hr - 1 + cy
@@ -201,7 +232,8 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
                     sidx = rd * TX + xd
                     assert np.all(~ok | ((sidx >= 0) & (sidx < NI))), "slab push"
                     np.add.at(slab[i], sidx[ok & real], 1)
-                    np.add.at(pushed[i], sidx[ok & computing], 1)
+                    # the x-split kernel pushes from real lanes only
+                    np.add.at(pushed[i], sidx[ok & computing & (real if XT else True)], 1)
             # every interior cell receives each direction from exactly one real
             # halo cell, and every slab slot is written by a computing wave
             assert np.all(slab == 1), ("slab coverage", slab.min(), slab.max())
@@ -212,10 +244,10 @@ def check(nx, ny, nz, TY, SZ, lat, full=True, NT=512, TXMAX=None):
             z = max(p - 1, z0)
             assert 0 <= z < nz
             for k in range(IPT):
-                own = (tid + k * NT < NI) & (p > z0)
-                cell = np.minimum(tid + k * NT, NI - 1)
-                r = cell // TX
-                cx_ = cell - r * TX
+                r, cx_, owned = interior_map(k)
+                own = owned & (p > z0)
+                cell = r * TX + cx_
+                assert np.all((cell >= 0) & (cell < NI)), "slab read"
                 x = x0 + cx_
                 y = y0 + r
                 assert np.all((y < ny) & (x < nx))
@@ -282,13 +314,15 @@ def test_two_step_tile_indexing_1024_threads(case):
 
 
 # x-split general tiles of the batched launch: (nx, ny, nz, rows, planes, cols)
-XT_CASES = [(192, 20, 9, 16, 4, 32), (192, 11, 7, 5, 3, 96), (130, 9, 6, 6, 5, 44),
-            (129, 7, 5, 10, 2, 43), (256, 6, 4, 4, 4, 64), (100, 12, 3, 13, 2, 34),
-            (64, 8, 4, 8, 4, 64), (33, 5, 4, 5, 2, 33), (8, 5, 3, 2, 2, 3),
-            # the tiles the batched launch picks (FP64 192, 257, 360 wide;
-            # FP32 360 wide)
-            (192, 20, 9, 8, 4, 48), (257, 5, 4, 5, 4, 65), (360, 7, 5, 7, 2, 52),
-            (360, 7, 5, 7, 5, 72)]
+XT_CASES = [(130, 9, 6, 6, 5, 44), (129, 7, 5, 10, 2, 43), (100, 12, 3, 13, 2, 34),
+            (8, 5, 3, 2, 2, 3), (61, 17, 4, 14, 3, 31), (70, 3, 2, 3, 2, 62),
+            # members that keep full rows in a launch with x-split members
+            (64, 8, 4, 8, 4, 64), (33, 5, 4, 5, 2, 33), (40, 12, 10, 12, 5, 40),
+            (96, 9, 3, 8, 3, 96),
+            # the tiles the batched launch picks: FP64 192, 257 wide (6 rows);
+            # reduced storage 360 wide (14 rows), and 192 wide
+            (192, 20, 9, 6, 4, 48), (257, 5, 4, 5, 4, 52), (360, 7, 5, 7, 2, 60),
+            (360, 30, 3, 14, 3, 60), (192, 20, 9, 14, 4, 48)]
 
 
 # general tiles of batches of narrow members: 768-thread blocks, one

@@ -256,34 +256,18 @@ def test_two_step_batch_compile_time_tiles_bitwise(group, lat, dtype):
         s.close()
 
 
-def _full_rows(nx, ny, f64):
-    """Rows of a full-row general tile: 512 interior and 1024 (FP64: 512)
-    halo-plane cells per block."""
-    r = 512 // nx - 2 if f64 else min(512 // nx, 1024 // nx - 2)
-    r = min(r, ny)
-    return r if r >= 1 else 0
-
-
 def _xt_tile(nx, ny, f64):
-    """(columns, rows) of a member's general tile in a batch with x-split
-    members: full rows where they fit a block, else the split into k >= 2
-    segments of at least 48 columns (a halo column on each side) with the
-    most interior cells per loaded cell."""
-    full = _full_rows(nx, ny, f64)
-    if full:
-        return nx, full
-    best, best_c, best_r = 0.0, 0, 0
-    for k in range(2, 17):
-        c = -(-nx // k)
-        if c < 48:
-            break
-        r = min(512 // c, (512 if f64 else 1024) // (c + 2) - 2, ny)
-        if r < 1:
-            continue
-        e = c * r / ((c + 2) * (r + 2))
-        if e > best:
-            best, best_c, best_r = e, c, r
-    return best_c, best_r
+    """(columns, rows) of a member's tile in a batch with x-split members,
+    whose kernel has one interior and one halo cell per thread (FP64) or two
+    and two: full rows where they fit (FP64 up to 170 wide, reduced storage
+    up to 341), else the fewest segments of at most 62 columns, one wave per
+    row, and 6 (FP64) or 14 rows."""
+    per = 1 if f64 else 2
+    full = min(per * 512 // nx - 2, ny)
+    if nx <= (170 if f64 else 341) or nx <= 62:
+        return (nx, full) if full >= 1 else (0, 0)
+    k = -(-nx // 62)
+    return -(-nx // k), min(per * 8 - 2, ny)
 
 
 @pytest.mark.parametrize("dtype", [vanse.FP32_SHIFTED, vanse.FP16_SHIFTED, vanse.FX16_SHIFTED])
@@ -365,9 +349,10 @@ def test_uniform_batch_of_one_128_cube_takes_shorter_segments_bitwise(dtype):
 
 
 # members whose full x-rows do not fit a block (FP64: 192, 257 and 360
-# wide; FP32/FP16: 360 wide) make the batched two-step launch split their
-# x-rows into segments of 48 or more columns with a halo column on each side;
-# the other members keep full rows in the same launch
+# wide; reduced storage: 360 wide) make the batched two-step launch split
+# their x-rows into segments of at most 62 columns with a halo column on each
+# side (one wave per row); the other members keep full rows in the same
+# launch
 XT_MEMBERS = [((192, 20, 9), 0.6, 11), ((160, 13, 7), 0.8, 12), ((130, 9, 6), 0.7, 13),
               ((40, 12, 10), 0.9, 14), ((257, 5, 4), 0.66, 15), ((360, 7, 5), 0.75, 16)]
 
@@ -395,8 +380,7 @@ def test_two_step_batch_x_split_tiles_bitwise(dtype, steps, chunk):
     split = [c < d[0] for (c, _, _), (d, _, _) in zip(tiles, XT_MEMBERS)]
     assert split == ([True, False, False, False, True, True] if f64 else
                      [False, False, False, False, False, True])
-    if not f64:
-        assert want_tiles[5] == (72, 7)
+    assert want_tiles[5] == ((60, 6) if f64 else (60, 7))
     assert [(r, p) for _, r, p in tiles] == b.two_step_layout()
     b.step(steps)
     for k, s in enumerate(members):
