@@ -231,10 +231,10 @@ int vanse_batch_set_stream(vanse_batch_t b, void *stream);
  *       reduced storage whose members are all at most 96 cells wide takes
  *       768-thread blocks instead, with as many x-rows as fit 768
  *       halo-plane cells (more rows per tile).  On D3Q19, when a member's
- *       full rows do not fit a block (nx > 340; FP64 nx > 170), general
- *       tiles split the x-rows of wide members into segments of at least
- *       48 columns with a halo column on each side
- *       (vanse_batch_two_step_tiles reports them).  Every member gets a
+ *       full rows do not fit a block (nx > 341; FP64 nx > 170), general
+ *       tiles split the x-rows of wide members into the fewest segments of
+ *       at most 62 columns, with a halo column on each side (one wave per
+ *       row; vanse_batch_two_step_tiles reports them).  Every member gets a
  *       second population array (allocated here, kept by the member's
  *       solver: its population memory doubles).  Used for every group of 4
  *       steps of a chunk while all members sit at even time levels (two
