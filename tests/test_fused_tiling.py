@@ -348,3 +348,44 @@ def test_two_step_x_split_tile_indexing(case, lat):
     full rows (cols >= nx)."""
     nx, ny, nz, rows, planes, cols = case
     assert check(nx, ny, nz, rows, planes, D3Q19, TXMAX=cols)
+
+
+def _chosen_tiles(nx, ny, f64):
+    """The batched launch's tile for a member of width nx: (threads, rows,
+    columns) of the 512-thread general tile, the 768-thread one (reduced
+    storage, nx <= 96) and the x-split launch's tile, as the host chooses
+    them (batch_fused_rows, batch_xt_tile)."""
+    out = []
+    r512 = min(512 // nx - 2 if f64 else min(512 // nx, 1024 // nx - 2), ny)
+    if r512 >= 1:
+        out.append((512, r512, nx))
+    if not f64 and nx <= 96:
+        r768 = min(768 // nx - 2, ny)
+        if r768 >= 1:
+            out.append((768, r768, nx))
+    per = 1 if f64 else 2
+    if nx > (170 if f64 else 341) and nx > 62:
+        k = -(-nx // 62)
+        out.append((512, min(per * 8 - 2, ny), -(-nx // k)))
+    else:
+        rf = min(per * 512 // nx - 2, ny)
+        if rf >= 1:
+            out.append((512, rf, -1))   # full rows inside an x-split launch
+    return out
+
+
+def test_random_sizes_tile_indexing():
+    """Every tile the batched launch can choose, for seeded random member
+    sizes, keeps every access in bounds and covers every output once."""
+    rng = np.random.default_rng(2208)
+    for _ in range(40):
+        f64 = bool(rng.integers(0, 2))
+        nx = int(rng.integers(3, 420))
+        ny = int(rng.integers(1, 24))
+        nz = int(rng.integers(1, 6))
+        for nt, rows, cols in _chosen_tiles(nx, ny, f64):
+            planes = int(rng.integers(1, nz + 1))
+            txmax = None if cols == nx else (nx if cols < 0 else cols)
+            assert check(nx, ny, nz, rows, planes, D3Q19, full=True, NT=nt, TXMAX=txmax), \
+                (nx, ny, nz, rows, planes, nt, cols)
+
