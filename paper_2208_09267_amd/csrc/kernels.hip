@@ -81,6 +81,7 @@ template <> struct Storage<MODE_F64> {
     using T = double;
     using R = double;
     static constexpr bool shifted = false, scaled = false, unit_c = false;
+    static constexpr double unit = 1.0;   // decoded values are in units of `unit`
     static __device__ __forceinline__ R decode(T v) { return v; }
     static __device__ __forceinline__ T encode(R v) { return v; }
 };
@@ -88,6 +89,7 @@ template <> struct Storage<MODE_F32S> {
     using T = float;
     using R = float;
     static constexpr bool shifted = true, scaled = false, unit_c = false;
+    static constexpr double unit = 1.0;
     static __device__ __forceinline__ R decode(T v) { return v; }
     static __device__ __forceinline__ T encode(R v) { return v; }
 };
@@ -95,6 +97,7 @@ template <> struct Storage<MODE_F16S> {
     using T = unsigned short;
     using R = float;
     static constexpr bool shifted = true, scaled = true, unit_c = true;
+    static constexpr double unit = 1.0;
     static __device__ __forceinline__ R decode(T v) { return __half2float(__ushort_as_half(v)); }
     static __device__ __forceinline__ T encode(R v) { return __half_as_ushort(__float2half_rn(v)); }
 };
@@ -102,13 +105,18 @@ template <> struct Storage<MODE_FX16S> {
     using T = unsigned short;
     using R = float;
     static constexpr bool shifted = true, scaled = true, unit_c = true;
-    static __device__ __forceinline__ R decode(T v) { return float((short)v) * (1.0f / 32768.0f); }
+    // the collision works on 2^15 v_i directly (the code's integer as a
+    // float): a scaling by a power of two, exact, so its results are those
+    // of decoding to v_i, with one multiplication per cell instead of one per
+    // value and direction
+    static constexpr double unit = 1.0 / 32768.0;
+    static __device__ __forceinline__ R decode(T v) { return float((short)v); }
     // round to nearest even, then saturate (a NaN saturates too: fmaxf
     // returns the other operand), so that an out-of-range value reads back
     // at the bound, which to_f64 reports as not a number
     static __device__ __forceinline__ T encode(R v)
     {
-        const float q = fminf(fmaxf(rintf(v * 32768.0f), -32767.0f), 32767.0f);
+        const float q = fminf(fmaxf(rintf(v), -32767.0f), 32767.0f);
         return (unsigned short)(short)(int)q;
     }
 };
@@ -123,7 +131,7 @@ __device__ __forceinline__ double to_f64(typename Storage<MODE>::T raw, double c
     if constexpr (MODE == MODE_FX16S) {
         if (raw == 0x7fffu || raw == 0x8000u || raw == 0x8001u) return __builtin_nan("");
     }
-    const double v = double(St::decode(raw));
+    const double v = double(St::decode(raw)) * St::unit;
     if constexpr (!St::shifted) return v;
     else if constexpr (!St::scaled) return L::w[I] + v;
     else if constexpr (!St::unit_c) return L::w[I] + L::w[I] * v;
@@ -338,6 +346,13 @@ __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R o
             if constexpr (i == first_dir<L, 2>()) jz = t; else jz = jz + t;
         }
     });
+    // sums of the stored values, in their units (FX16: 2^-15)
+    if constexpr (St::unit != 1.0) {
+        s0 = s0 * R(St::unit);
+        jx = jx * R(St::unit);
+        jy = jy * R(St::unit);
+        jz = jz * R(St::unit);
+    }
     const R M0 = St::shifted ? R(1) + s0 : s0;
     // eq. density and the 1/M0 of eq. velocity.  In the 16-bit modes, whose
     // rounding dominates the error, the hardware reciprocal (about 1 ulp of
@@ -363,11 +378,14 @@ __device__ __forceinline__ void collide(R (&v)[L::Q], R I, R gx, R gy, R gz, R o
 
     const R om1 = R(1) - omega;
     const R E = St::shifted ? s0 - R(1.5) * uu * M0 : M0 * (R(1) - R(1.5) * uu);
-    const R P0 = omega * E - R(3) * fcoef * uF;
-    const R a45 = R(4.5) * omega * M0;
-    const R b9 = R(9) * fcoef;
-    const R c3 = R(3) * omega * M0;
-    const R d3 = R(3) * fcoef;
+    // the update's coefficients in the units of the stored values (exact:
+    // 1/unit is a power of two)
+    constexpr R IU = R(1.0 / St::unit);
+    const R P0 = (omega * E - R(3) * fcoef * uF) * IU;
+    const R a45 = R(4.5) * omega * M0 * IU;
+    const R b9 = R(9) * fcoef * IU;
+    const R c3 = R(3) * omega * M0 * IU;
+    const R d3 = R(3) * fcoef * IU;
     {
         // The collision conserves M0: sum_i W_i (P0 + ...) = P0 in exact
         // arithmetic.  With the weights rounded to R their sum is 1 + delta
@@ -1123,7 +1141,8 @@ __global__ void __launch_bounds__(256) init_kernel(StepArgs a, const double *__r
         else if constexpr (!Storage<MODE>::scaled)
             f[i * a.geo.stride + c] = Storage<MODE>::encode(R(feq - L::w[i]));
         else
-            f[i * a.geo.stride + c] = Storage<MODE>::encode(R(feq / (a.shift * L::w[i]) - 1.0));
+            f[i * a.geo.stride + c] =
+                Storage<MODE>::encode(R((feq / (a.shift * L::w[i]) - 1.0) / Storage<MODE>::unit));
     });
 }
 
