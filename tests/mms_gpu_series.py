@@ -4,7 +4,7 @@ pressure (physical units; L1, L2, Linf) once stabilised, and the order
 between consecutive resolutions.  Same driver as tests/test_gpu_mms.py.
 
 Usage (one MI355X): python tests/mms_gpu_series.py OUT.json EX:N1,N2,...:T_END ...
-e.g. python tests/mms_gpu_series.py gpurun_out/mms.json 4:36,48,72,96:10 5:24,32,48,64:8
+e.g. python tests/mms_gpu_series.py mms.json 4:36,48,72,96:10 5:24,32,48,64:8
 """
 import json
 import os
