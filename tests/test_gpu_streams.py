@@ -3,7 +3,8 @@ the binding enqueues every call on torch's current stream, so a solve run
 inside `torch.cuda.stream(side)` must produce exactly what it produces on the
 default stream.  Covers the calls that synchronise on the handle's stream
 (the 16-bit modes' init reduction, diagnostics), the two-step launch and a
-graph-captured batch, for FP64, FP32 shifted and FP16.
+graph-captured batch, for FP64, FP32 shifted and FP16; and two solves whose
+launches interleave on two streams end where each ends alone.
 """
 import numpy as np
 import pytest
@@ -54,3 +55,47 @@ def test_side_stream_results_equal_the_default_stream(dtype):
     torch.cuda.current_stream().wait_stream(side)
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
+
+
+def test_two_solves_interleaved_on_two_streams_equal_sequential_runs():
+    """Handles share no device state: two solves whose launches are enqueued
+    alternately on two streams (so they may overlap on the device) end
+    bitwise where each ends alone."""
+    dims = (64, 16, 12)
+    pert = torch.from_numpy(W.fourier_eps(dims, seed=9)).cuda()
+    u0 = torch.from_numpy(np.ascontiguousarray(W.taylor_green(dims, 0.02))).cuda()
+
+    def make(tau, dtype, fused):
+        s = vanse.Solver("D3Q19", dims, tau, dtype)
+        s.set_porosity(0.75, pert, 13.0)
+        s.init(None, u0)
+        if fused:
+            s.set_fused(4, 4)
+        return s
+
+    cases = [(0.6, vanse.FP32_SHIFTED, True), (0.9, vanse.FP16_SHIFTED, False)]
+    alone = []
+    for c in cases:
+        s = make(*c)
+        s.step(24)
+        alone.append(s.populations().cpu().numpy())
+        s.close()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    solvers = []
+    for c, st in zip(cases, streams):
+        with torch.cuda.stream(st):
+            solvers.append(make(*c))
+    for _ in range(12):
+        for s, st in zip(solvers, streams):
+            with torch.cuda.stream(st):
+                s.step(2)
+    for s, st, ref in zip(solvers, streams, alone):
+        with torch.cuda.stream(st):
+            got = s.populations().cpu().numpy()
+        assert np.array_equal(got, ref)
+    for st in streams:
+        torch.cuda.current_stream().wait_stream(st)
+    for s in solvers:
+        s.close()
