@@ -567,7 +567,13 @@ int vanse_autotune(vanse_t h, int steps_per_trial, int *tile_x, int *tile_y, int
     {
         std::lock_guard<std::mutex> lk(g_solo_tune_mu);
         auto it = g_solo_tune_cache.find(key);
-        if (it != g_solo_tune_cache.end()) {
+        // the class key does not fix ny: a two-step tile chosen on another
+        // lattice of the class may have more rows than this one (or no
+        // compiled shape here), and is then tuned again
+        if (it != g_solo_tune_cache.end() &&
+            (it->second.fused_rows == 0 ||
+             (it->second.fused_rows <= s.geo.ny &&
+              vanse::fused_shape(s.lattice, s.mode, s.geo, it->second.fused_rows, nullptr)))) {
             best_c = it->second;
             cached = true;
         }

@@ -307,6 +307,31 @@ def test_autotune_is_bitwise_neutral_and_counts_its_steps():
     b.close()
 
 
+def test_cached_choice_with_more_rows_than_the_lattice_is_tuned_again():
+    """The autotuner caches its choice per size class (lattice, dtype, log2
+    of the cells, nx, ny mod 8), which does not fix ny: a lattice of the
+    class with fewer rows than the cached two-step tile gets a choice of its
+    own instead of an error."""
+    def make(dims):
+        s = vanse.Solver("D3Q19", dims, 0.6, vanse.FP32_SHIFTED)
+        s.set_porosity(0.75, torch.from_numpy(W.fourier_eps(dims, seed=5)).cuda(), 40.0)
+        s.init(None, torch.from_numpy(np.ascontiguousarray(W.taylor_green(dims, 0.02))).cuda())
+        return s
+
+    a = make((256, 9, 7282))   # 16 777 728 cells; its two-step tiles have 1 or 2 rows
+    la = a.autotune(2)
+    b = make((256, 1, 65536))  # 16 777 216 cells: the same class, ny = 1
+    lb = b.autotune(2)
+    print("choices", la, lb, flush=True)
+    assert lb.fused_rows <= 1
+    if la.fused_rows > 1:
+        assert lb.steps_run > 0  # tuned again, not taken from the cache
+    b.step(6)
+    assert np.isfinite(b.diagnostics()[0])
+    a.close()
+    b.close()
+
+
 # (storage, two-step rows, planes, tolerances on rho, p, u and on p against
 # the stricter scale |p - mean p|).  FP64: the 1e-11 bar.  The reduced
 # modes: about twice their recorded full-field errors against FP64 after
