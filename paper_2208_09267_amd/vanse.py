@@ -167,6 +167,17 @@ def diagnostics_noalloc(lattice, dims, f, phi, quad_axes=0, F=None, force=None, 
     arr = (ctypes.c_int64 * 3)(*[int(v) for v in dims])
     if out is None:
         out = torch.empty(7, dtype=torch.float64, device=f.device)
+    # the library takes plain device pointers and cannot see their sizes:
+    # check them here (an unknown lattice or bad dims is the library's EINVAL)
+    q = {D2Q9: 9, D3Q19: 19, D3Q27: 27}.get(lattice)
+    if q is not None and all(int(v) >= 1 for v in dims):
+        n = int(dims[0]) * int(dims[1]) * int(dims[2])
+        d = 2 if lattice == D2Q9 else 3
+        for name, t, want in (("f", f, q * n), ("phi", phi, n), ("force", force, d * n)):
+            if t is not None and t.numel() != want:
+                raise ValueError("%s must have %d values, not %d" % (name, want, t.numel()))
+    if out.numel() < 7:
+        raise ValueError("out must hold 7 values")
     Fh = None if F is None else (ctypes.c_double * 3)(*[float(v) for v in list(F) + [0.0] * (3 - len(F))])
     rc = lib.vanse_diagnostics_noalloc(lattice, arr, _ptr(f), _ptr(phi), int(quad_axes), Fh,
                                        _ptr(force), _ptr(out), _stream_handle())

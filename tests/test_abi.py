@@ -104,3 +104,22 @@ def test_library_d3q27_matches_paper_table2():
         assert lut[tuple(c)] == wi
     for i in range(1, 14):
         assert np.array_equal(-np.array(xi[i]), np.array(xi[i + 13]))
+
+
+def test_noalloc_binding_checks_buffer_sizes():
+    """The C entry point takes plain device pointers; the binding checks the
+    tensors' sizes before any device call (host-only: these raise on the CPU)."""
+    import torch
+    from paper_2208_09267_amd import vanse
+    dims = (4, 3, 2)
+    n = 24
+    f = torch.zeros(19 * n, dtype=torch.float64)
+    phi = torch.zeros(n, dtype=torch.float64)
+    out = torch.zeros(7, dtype=torch.float64)
+    cases = [(torch.zeros(19 * n - 1, dtype=torch.float64), phi, None, out, "f must have"),
+             (f, torch.zeros(n + 1, dtype=torch.float64), None, out, "phi must have"),
+             (f, phi, torch.zeros(2 * n, dtype=torch.float64), out, "force must have"),
+             (f, phi, None, torch.zeros(6, dtype=torch.float64), "out must hold")]
+    for ff, pp, force, oo, needle in cases:
+        with pytest.raises(ValueError, match=needle):
+            vanse.diagnostics_noalloc("D3Q19", dims, ff, pp, force=force, out=oo)
