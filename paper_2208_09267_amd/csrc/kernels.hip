@@ -111,13 +111,19 @@ template <> struct Storage<MODE_FX16S> {
     // value and direction
     static constexpr double unit = 1.0 / 32768.0;
     static __device__ __forceinline__ R decode(T v) { return float((short)v); }
-    // round to nearest even, then saturate (a NaN saturates too: fmaxf
-    // returns the other operand), so that an out-of-range value reads back
-    // at the bound, which to_f64 reports as not a number
+    // saturate at +-32767, then round to nearest even, so that an
+    // out-of-range value reads back at the bound, which to_f64 reports as
+    // not a number.  The clamp is the median of three, which takes a NaN
+    // to -32767 (in IEEE mode its minimum of three drops a NaN operand).
+    // Adding 1.5 * 2^23 to the clamped value leaves the nearest-even integer
+    // in the low mantissa bits (the sum lies in [2^23, 2^24), where the
+    // spacing is 1), so the low 16 bits of the sum's bit pattern are the
+    // int16 code: the code of rounding, clamping and converting, in two
+    // instructions instead of four.
     static __device__ __forceinline__ T encode(R v)
     {
-        const float q = fminf(fmaxf(rintf(v), -32767.0f), 32767.0f);
-        return (unsigned short)(short)(int)q;
+        const float c = __builtin_amdgcn_fmed3f(v, -32767.0f, 32767.0f);
+        return (unsigned short)__float_as_uint(c + 12582912.0f);
     }
 };
 
